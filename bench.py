@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Throughput of the DPD step (particle-steps/s) on one MI355X.
+
+Workload: the large single-species fluid, L = 96 periodic, rho = 3
+(2,654,208 particles), a = 25, gamma = 4.5, sigma = 3, dt = 0.04, FP32 forces
+and velocities with FP64 positions, uniform random start (seeded, synthetic).
+
+One step is the whole hot path: integrate-1, cell binning, pair force
+F^C + F^D + F^R with Philox noise, bonds (none here), integrate-2.  The timed
+region runs `--steps` consecutive steps with the state resident in HBM,
+bracketed by HIP events on the library's stream.
+
+Prints one JSON line: metric, value, roofline of the dominant kernel and the
+CPU baseline (the FP64 oracle on the host cores, on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per particle-step in mixed precision: the persistent
+# state (FP64 position 24 B, FP32 velocity 12 B and force 12 B, tag 4 B,
+# type 4 B) read once and written once.
+B_ALG_MIXED = 112.0
+B_ALG_FP64 = 160.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="fluid_L96",
+                    choices=["fluid_L96", "fluid_L10", "melt_L32", "peptide_L40"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many steps (for rocprofv3), print nothing else")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from paper_1804_06205_amd import workloads as W
+    return {"fluid_L96": W.cfg_fluid_L96, "fluid_L10": W.cfg_fluid_L10,
+            "melt_L32": W.cfg_melt_L32, "peptide_L40": W.cfg_peptide_L40}[name]()
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle (FP64, OpenMP) on the host cores, stepped until budget_s."""
+    import oracle
+    st = oracle.State.from_workload(w)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        st.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 1000:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.n * steps / el, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} step(s) of the same {w.name} box ({w.n} particles) after its "
+                      f"initial force, FP64, {threads} OpenMP threads, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1804_06205_amd import dpd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    stream = torch.cuda.Stream()
+    g = dpd.System.from_workload(w, stream=stream)
+    if args.profile_steps:
+        g.step(args.profile_steps)
+        g.sync()
+        print(f"profiled {args.profile_steps} steps of {w.name}", flush=True)
+        return
+
+    g.step(args.warmup)
+    g.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(args.steps)
+    e1.record(stream)
+    g.sync()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    value = w.n * args.steps / (ms / 1e3)
+
+    # Per-kernel device time of the same step sequence (events around each
+    # launch, same stream).
+    kt = g.step_profiled(args.steps)
+    fused_ms = kt["ms_fused"] / max(1, kt["n_fused"])
+    b_alg = B_ALG_FP64 if w.precision == "fp64" else B_ALG_MIXED
+    achieved = b_alg * w.n / (fused_ms / 1e3) / 1e9
+    info = g.info()
+    obs = g.observables()
+    g.close()
+
+    line = {
+        "metric": "particle-steps/s (DPD step, rho=3)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "particles": w.n, "box": list(w.L), "rho": 3,
+                   "a": float(w.a[0, 0]), "gamma": w.gamma, "sigma": w.sigma, "dt": w.dt,
+                   "precision": "FP32 forces/velocities, FP64 positions"
+                   if w.precision == "mixed" else "FP64",
+                   "cell_capacity": info["cell_capacity"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_force (fused)", "kernel_ms": fused_ms,
+                     "bytes_per_particle_step": b_alg},
+        "kernel_ms": {"begin": kt["ms_begin"] / max(1, kt["n_begin"]), "fused": fused_ms,
+                      "finish": kt["ms_finish"] / max(1, kt["n_finish"])},
+        "final_kT": obs["kT"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * dpd.h - C ABI of the MI355X (gfx950) DPD step library.
+ *
+ * One call of dpd_step advances a periodic box of soft beads by Groot-style
+ * dissipative particle dynamics as defined by Doi et al., "A portable code for
+ * dissipative particle dynamics (DPD) simulations with additional specific
+ * interactions" (arXiv 1804.06205):
+ *   - the total force of Eq. (3): conservative F^C (Eq. 4), dissipative F^D and
+ *     random F^R (the Groot-Warren forms the text after Eq. 5 refers to), and
+ *     the bonded F^S of Eq. (8): harmonic springs (Eq. 6) and Morse terms
+ *     (Eq. 7 and the standard form);
+ *   - pairs taken straight from cells of edge rc = 1 rebuilt every step, with
+ *     no stored neighbour list (design section of the paper);
+ *   - Groot's modified velocity Verlet (Fig. 1):
+ *       x <- x + dt v + dt^2 f / 2, wrap;  vt <- v + lambda dt f;
+ *       f' <- F(x, vt; s);  v <- v + dt (f + f') / 2;  f <- f'.
+ *
+ * Units: masses 1, cutoff rc = 1.  Particles are named by their tag, the
+ * index 0..n-1 of the arrays passed to dpd_create; every state array crossing
+ * this ABI is in tag order, row-major (n, 3).
+ *
+ * The random force of pair (i, j) at force evaluation s (0 for the initial
+ * force, k for the force at the end of step k) uses theta = sqrt(-2 ln u1)
+ * cos(2 pi u2) from Philox4x32-10 with key = seed and counter
+ * (min(tag_i, tag_j), max(tag_i, tag_j), s mod 2^32, 0), u1 = ((w0 >> 8) + 1)
+ * 2^-24 and u2 = (w1 >> 8) 2^-24, so theta_ij = theta_ji and a run is
+ * reproducible bit for bit.
+ *
+ * Memory: the library copies every host array at the call and never keeps a
+ * caller pointer.  It owns all device memory it allocates and frees it in
+ * dpd_destroy.  Work is enqueued on one HIP stream per system (the caller's,
+ * or one the library creates); dpd_step returns after enqueueing.
+ *
+ * Errors: every int-returning call returns DPD_OK (0) or a negative code and
+ * leaves a message for dpd_last_error() (per thread).  Device-side failures
+ * (a cell or tile capacity exceeded, a non-finite value, a displacement over
+ * half a box) are sticky: they surface at the next synchronising call
+ * (dpd_sync, dpd_observables, dpd_get_state, dpd_get_cells) and every later
+ * call on that system fails with the same code.
+ *
+ * Threading: one system must not be used from two threads at once; separate
+ * systems are independent.
+ */
+#ifndef DPD_H
+#define DPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPD_ABI_VERSION 1
+
+typedef struct dpd_system dpd_system;
+
+enum dpd_status {
+    DPD_OK = 0,
+    DPD_EINVAL = -1,     /* bad argument: n < 2, non-finite input, gamma or sigma < 0,
+                            dt <= 0, lambda outside [0, 1], bad type or precision     */
+    DPD_ENOMEM = -2,     /* device or host allocation failed                          */
+    DPD_EDEVICE = -3,    /* HIP runtime error, or no gfx950 device                     */
+    DPD_ENUMERIC = -4,   /* non-finite state, or a displacement over half a box        */
+    DPD_EBOX = -5,       /* some box edge below 3 cells (L < 3 rc)                     */
+    DPD_ERANGE = -6,     /* bond tag out of range or i == j, or bond length >= L/2     */
+    DPD_ESTATE = -7,     /* parameters or bonds changed after the first step, or a call
+                            before dpd_set_params                                      */
+    DPD_EBUSY = -8,      /* batch full or over its memory budget                       */
+    DPD_ECAPACITY = -9   /* a cell held more particles than its slots (local density far
+                            above the box average); recreate with a larger cell_capacity */
+};
+
+enum dpd_precision {
+    DPD_PREC_FP64 = 0,   /* FP64 throughout                                            */
+    DPD_PREC_MIXED = 1   /* FP32 forces and velocities, FP64 positions                  */
+};
+
+enum dpd_bond_type {
+    DPD_BOND_HARMONIC = 1,    /* Eq. (6): F_i = -C (r - r_e) e, U = C (r - r_e)^2 / 2  */
+    DPD_BOND_MORSE_PAPER = 2, /* Eq. (7) with the alpha of Fig. 3a: E = exp(-alpha |r - r_e|),
+                                 F_i = -2 alpha K E (1 - E) e (attractive on both sides of
+                                 r_e), U = K (1 - E)^2 as Fig. 3a accumulates it          */
+    DPD_BOND_MORSE = 3        /* standard Morse: E = exp(-alpha (r - r_e)),
+                                 U = D [(1 - E)^2 - 1], F_i = -2 alpha D E (1 - E) e      */
+};
+
+/* Observables of the current state (FP64 sums; pressure per the virial of the
+ * conservative and bonded forces, p = (2 KE + W) / (3 V)). */
+typedef struct dpd_obs {
+    int64_t step;        /* steps taken since the state's step counter was 0   */
+    double time;         /* step * dt                                          */
+    double ke;           /* sum |v|^2 / 2                                      */
+    double kT;           /* 2 KE / (3N - 3)                                    */
+    double u_pair;       /* sum over pairs r < 1 of a (1 - r)^2 / 2            */
+    double u_bond;       /* bonded energy (Fig. 3a accumulates it as Ebond)    */
+    double w_pair;       /* sum over pairs of d . F^C                          */
+    double w_bond;       /* sum over bonds of d . F^S                          */
+    double pressure;
+    double momentum[3];  /* sum v                                              */
+    int64_t npairs;      /* unordered pairs with r^2 < 1 (in the force precision) */
+} dpd_obs;
+
+/* Per-kernel timing of dpd_step_profiled, in milliseconds summed over launches. */
+typedef struct dpd_kernel_times {
+    double ms_begin;     /* integrate-1 + binning from the resting state       */
+    double ms_fused;     /* pair + bond force, integrate-2, integrate-1, binning */
+    double ms_finish;    /* pair + bond force, integrate-2                      */
+    int64_t n_begin, n_fused, n_finish;  /* launch counts                       */
+} dpd_kernel_times;
+
+/* Library ABI version (DPD_ABI_VERSION). */
+int dpd_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  Owned by the
+ * library; valid until the next call on this thread. */
+const char *dpd_last_error(void);
+
+/*
+ * Creates a system of n particles in a periodic box of edges L[0..2] (each
+ * >= 3; cells per axis = floor(L), edge L / floor(L)).
+ *   pos, vel   host arrays of n*3 doubles (tag order); positions are wrapped
+ *              into [0, L) on entry.
+ *   type       host array of n bytes, each < ntypes, or NULL (all 0).
+ *   ntypes     1..16.
+ *   seed       key of the pair noise stream.
+ *   precision  DPD_PREC_FP64 or DPD_PREC_MIXED.
+ *   hip_stream a hipStream_t to enqueue on, or NULL for a library-owned one.
+ *   cell_capacity  slots per cell, or 0 for the default (32).
+ * On success *out owns the system; the step counter is 0 and the force is
+ * computed at the first step as F(x, v; s = 0).
+ */
+int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos,
+               const double *vel, const uint8_t *type, int ntypes, uint64_t seed,
+               int precision, void *hip_stream, int cell_capacity);
+
+/*
+ * Sets the pair table and integrator parameters.  a_ij: ntypes*ntypes doubles,
+ * row-major, must be symmetric (Eq. 4; Eq. 5 maps chi to a_ij on the caller's
+ * side).  gamma, sigma >= 0 (sigma^2 = 2 gamma kT is not enforced); kT is only
+ * reported back; dt > 0; lambda in [0, 1] (0.65 in the paper).  Allowed until
+ * the first step.
+ */
+int dpd_set_params(dpd_system *sys, const double *a_ij, double gamma, double sigma, double kT,
+                   double dt, double lambda);
+
+/*
+ * Adds nb bond records (Eq. 8; Fig. 3b's record [type, i, j, r_e, const,
+ * const2]): btype[b] in dpd_bond_type, tags i[b] != j[b] in [0, n), r_e, k (C,
+ * K_M or D) and alpha (ignored for harmonic).  Several records may sit on one
+ * pair; they all add.  Bonds have no cutoff and use the minimum image.  May be
+ * called several times before the first step.
+ */
+int dpd_add_bonds(dpd_system *sys, int64_t nb, const int32_t *btype, const int64_t *i,
+                  const int64_t *j, const double *r_e, const double *k, const double *alpha);
+
+/* Enqueues nsteps >= 0 steps on the system's stream and returns. */
+int dpd_step(dpd_system *sys, int64_t nsteps);
+
+/* Like dpd_step, but synchronises and reports per-kernel device time. */
+int dpd_step_profiled(dpd_system *sys, int64_t nsteps, dpd_kernel_times *out);
+
+/* Waits for the system's stream; returns any sticky device error. */
+int dpd_sync(dpd_system *sys);
+
+/* Computes the observables of the current state (synchronises). */
+int dpd_observables(dpd_system *sys, dpd_obs *out);
+
+/* Copies the current state to host arrays of n*3 doubles in tag order (any
+ * pointer may be NULL) and the step counter (may be NULL).  Synchronises. */
+int dpd_get_state(dpd_system *sys, double *pos, double *vel, double *force, int64_t *step);
+
+/* Replaces the state (pos and vel required; force NULL = recompute it as
+ * F(x, v; s = step) at the next step) and the step counter. */
+int dpd_set_state(dpd_system *sys, const double *pos, const double *vel, const double *force,
+                  int64_t step);
+
+/* The current cell list: cell_of_tag[n] = linear cell (cz ny + cy) nx + cx of
+ * each particle, count[ncells] = particles per cell.  Synchronises. */
+int dpd_get_cells(dpd_system *sys, int64_t *cell_of_tag, int64_t *count);
+
+/* Sizes of the system: out[0] = n, out[1] = ncells, out[2] = cell capacity,
+ * out[3] = device bytes held, out[4..6] = cells per axis, out[7] = precision. */
+int dpd_info(dpd_system *sys, int64_t out[8]);
+
+/* Frees the system and its device memory (NULL is ignored). */
+void dpd_destroy(dpd_system *sys);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPD_H */

@@ -1,0 +1,649 @@
+// C ABI of the DPD step library (include/dpd.h): system lifetime, parameter
+// and bond upload, the step schedule, state and observable read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dpd.h"
+#include "dpd_device.hpp"
+#include "dpd_kernels.hpp"
+
+using namespace dpd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(DPD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+template <typename T> size_t prec_size() { return sizeof(T); }
+
+}  // namespace
+
+struct dpd_system {
+    int prec = DPD_PREC_MIXED;
+    int64_t n = 0;
+    double L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    int nc[3] = {0, 0, 0};
+    int64_t ncells = 0;
+    int cap = 32;
+    int ntypes = 1;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    bool params_set = false;
+    std::vector<double> a;
+    double gamma = 0, sigma = 0, kT = 1, dt = 0, lambda = 0.65;
+
+    std::vector<int32_t> btype;
+    std::vector<int64_t> bi, bj;
+    std::vector<double> bre, bk, balpha;
+    bool frozen = false;
+
+    // Device memory.
+    void *P[2] = {nullptr, nullptr};
+    void *S[2] = {nullptr, nullptr};
+    uint32_t *slot_of_tag[2] = {nullptr, nullptr};
+    uint32_t *count[3] = {nullptr, nullptr, nullptr};
+    void *a_dev = nullptr;
+    uint32_t *bond_off = nullptr;
+    void *bonds = nullptr;
+    uint32_t *err = nullptr;
+    double *stage = nullptr;        // 9n doubles: x, v, f in tag order
+    int64_t *cell_stage = nullptr;  // n
+    uint8_t *type_dev = nullptr;
+    double *obs = nullptr;          // 9n doubles: per-tag observables
+    uint32_t *obs_np = nullptr;
+    double **obs_ptrs = nullptr;    // 8 device pointers for the reduction
+    double *red = nullptr;          // partial sums
+    int red_blocks = 0;
+    size_t bytes = 0;
+
+    int64_t t = 0;                  // state index of the resting state
+    bool force_valid = false;
+    int variant = 0;
+    int sticky = DPD_OK;
+    std::string sticky_msg;
+};
+
+namespace {
+
+template <typename T> DevSys<T> make_dev(const dpd_system *s) {
+    DevSys<T> D;
+    std::memset(&D, 0, sizeof D);
+    for (int k = 0; k < 3; ++k) {
+        D.L[k] = s->L[k];
+        D.h[k] = s->h[k];
+        D.nc[k] = s->nc[k];
+    }
+    D.cap = s->cap;
+    D.ncells = s->ncells;
+    D.n = s->n;
+    D.ntypes = s->ntypes;
+    D.dt = (T)s->dt;
+    D.lambda = (T)s->lambda;
+    D.gamma = (T)s->gamma;
+    D.sigma_rdt = s->dt > 0 ? (T)(s->sigma / std::sqrt(s->dt)) : (T)0;
+    D.dt_d = s->dt;
+    D.half_dt2_d = 0.5 * s->dt * s->dt;
+    D.seed = s->seed;
+    D.a = (const T *)s->a_dev;
+    for (int k = 0; k < 2; ++k) {
+        D.P[k] = (PRec<T> *)s->P[k];
+        D.S[k] = (SRec<T> *)s->S[k];
+        D.slot_of_tag[k] = s->slot_of_tag[k];
+    }
+    for (int k = 0; k < 3; ++k) D.count[k] = s->count[k];
+    D.bond_off = s->bond_off;
+    D.bonds = (const BondEnt<T> *)s->bonds;
+    D.err = s->err;
+    const int64_t n = s->n;
+    D.obs_u = s->obs;
+    D.obs_w = s->obs + n;
+    D.obs_ub = s->obs + 2 * n;
+    D.obs_wb = s->obs + 3 * n;
+    D.obs_ke = s->obs + 4 * n;
+    D.obs_p = s->obs + 6 * n;   // 3n, after the pair-count copy at 5n
+    D.obs_np = s->obs_np;
+    return D;
+}
+
+int dmalloc(dpd_system *s, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(DPD_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    s->bytes += bytes;
+    return DPD_OK;
+}
+
+void free_all(dpd_system *s) {
+    void *ptrs[] = {s->P[0], s->P[1], s->S[0], s->S[1], s->slot_of_tag[0], s->slot_of_tag[1],
+                    s->count[0], s->count[1], s->count[2], s->a_dev, s->bond_off, s->bonds,
+                    s->err, s->stage, s->cell_stage, s->type_dev, s->obs, s->obs_np,
+                    s->obs_ptrs, s->red};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+// Reads the device error word; converts it to a sticky status.
+int check_device(dpd_system *s) {
+    if (s->sticky != DPD_OK) return fail(s->sticky, "%s", s->sticky_msg.c_str());
+    HIP_OK(hipStreamSynchronize(s->stream));
+    uint32_t e = 0;
+    HIP_OK(hipMemcpy(&e, s->err, sizeof e, hipMemcpyDeviceToHost));
+    if (e == 0) return DPD_OK;
+    int code = DPD_EDEVICE;
+    const char *what = "internal index error";
+    if (e & ERR_CELL_OVERFLOW) {
+        code = DPD_ECAPACITY;
+        what = "a cell received more particles than its slots (raise cell_capacity)";
+    } else if (e & ERR_TILE_OVERFLOW) {
+        code = DPD_ECAPACITY;
+        what = "a brick's neighbourhood exceeded the tile buffer (local density too high)";
+    } else if (e & ERR_NONFINITE) {
+        code = DPD_ENUMERIC;
+        what = "non-finite position, velocity or force";
+    } else if (e & ERR_DISPLACEMENT) {
+        code = DPD_ENUMERIC;
+        what = "a particle moved more than half a box in one step";
+    }
+    s->sticky = code;
+    s->sticky_msg = std::string("device error: ") + what;
+    return fail(code, "%s", s->sticky_msg.c_str());
+}
+
+template <typename T> int upload_params(dpd_system *s) {
+    std::vector<T> a(s->a.begin(), s->a.end());
+    HIP_OK(hipMemcpyAsync(s->a_dev, a.data(), a.size() * sizeof(T), hipMemcpyHostToDevice,
+                          s->stream));
+    // Bond CSR over tags: each record appears at both of its ends.
+    const int64_t n = s->n, nb = (int64_t)s->btype.size();
+    if (nb > 0) {
+        std::vector<uint32_t> off(n + 1, 0);
+        for (int64_t b = 0; b < nb; ++b) {
+            off[s->bi[b] + 1]++;
+            off[s->bj[b] + 1]++;
+        }
+        for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
+        std::vector<BondEnt<T>> ent(2 * nb);
+        std::vector<uint32_t> fill(off.begin(), off.end() - 1);
+        for (int64_t b = 0; b < nb; ++b) {
+            BondEnt<T> e;
+            e.type = s->btype[b];
+            e.r_e = (T)s->bre[b];
+            e.k = (T)s->bk[b];
+            e.alpha = (T)s->balpha[b];
+            e.partner = (uint32_t)s->bj[b];
+            ent[fill[s->bi[b]]++] = e;
+            e.partner = (uint32_t)s->bi[b];
+            ent[fill[s->bj[b]]++] = e;
+        }
+        if (dmalloc(s, (void **)&s->bond_off, (n + 1) * sizeof(uint32_t))) return DPD_ENOMEM;
+        if (dmalloc(s, &s->bonds, ent.size() * sizeof(BondEnt<T>))) return DPD_ENOMEM;
+        HIP_OK(hipMemcpyAsync(s->bond_off, off.data(), off.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, s->stream));
+        HIP_OK(hipMemcpyAsync(s->bonds, ent.data(), ent.size() * sizeof(BondEnt<T>),
+                              hipMemcpyHostToDevice, s->stream));
+        // The host vectors must outlive the async copies.
+        HIP_OK(hipStreamSynchronize(s->stream));
+    } else {
+        HIP_OK(hipStreamSynchronize(s->stream));
+    }
+    return DPD_OK;
+}
+
+int freeze(dpd_system *s) {
+    if (s->frozen) return DPD_OK;
+    if (!s->params_set) return fail(DPD_ESTATE, "dpd_set_params must be called before stepping");
+    int rc = s->prec == DPD_PREC_FP64 ? upload_params<double>(s) : upload_params<float>(s);
+    if (rc) return rc;
+    s->frozen = true;
+    return DPD_OK;
+}
+
+template <typename T> int run_force(dpd_system *s, uint32_t q, int mode) {
+    const DevSys<T> D = make_dev<T>(s);
+    HIP_OK(launch_force<T>(D, q, mode, s->variant, s->stream));
+    return DPD_OK;
+}
+
+int force(dpd_system *s, uint32_t q, int mode) {
+    return s->prec == DPD_PREC_FP64 ? run_force<double>(s, q, mode) : run_force<float>(s, q, mode);
+}
+
+int begin(dpd_system *s, uint32_t q) {
+    if (s->prec == DPD_PREC_FP64) HIP_OK(launch_begin<double>(make_dev<double>(s), q, s->stream));
+    else HIP_OK(launch_begin<float>(make_dev<float>(s), q, s->stream));
+    return DPD_OK;
+}
+
+int ensure_force(dpd_system *s) {
+    if (s->force_valid) return DPD_OK;
+    int rc = force(s, (uint32_t)s->t, FORCE_INIT);
+    if (rc) return rc;
+    s->force_valid = true;
+    return DPD_OK;
+}
+
+// Uploads host state (tag order) and bins it as state t.
+int load_state(dpd_system *s, const double *pos, const double *vel, const double *frc,
+               int64_t t) {
+    const int64_t n = s->n;
+    HIP_OK(hipMemcpyAsync(s->stage, pos, 3 * n * sizeof(double), hipMemcpyHostToDevice,
+                          s->stream));
+    HIP_OK(hipMemcpyAsync(s->stage + 3 * n, vel, 3 * n * sizeof(double), hipMemcpyHostToDevice,
+                          s->stream));
+    if (frc)
+        HIP_OK(hipMemcpyAsync(s->stage + 6 * n, frc, 3 * n * sizeof(double),
+                              hipMemcpyHostToDevice, s->stream));
+    for (int k = 0; k < 3; ++k) HIP_OK(launch_fill_u32(s->count[k], s->ncells, 0u, s->stream));
+    const uint32_t q = (uint32_t)t;
+    if (s->prec == DPD_PREC_FP64)
+        HIP_OK(launch_load<double>(make_dev<double>(s), q, s->stage, s->stage + 3 * n,
+                                   frc ? s->stage + 6 * n : nullptr, s->type_dev, s->stream));
+    else
+        HIP_OK(launch_load<float>(make_dev<float>(s), q, s->stage, s->stage + 3 * n,
+                                  frc ? s->stage + 6 * n : nullptr, s->type_dev, s->stream));
+    // The host arrays may be released by the caller after return.
+    HIP_OK(hipStreamSynchronize(s->stream));
+    s->t = t;
+    s->force_valid = frc != nullptr;
+    return DPD_OK;
+}
+
+bool all_finite(const double *p, int64_t m) {
+    for (int64_t i = 0; i < m; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int check_usable(dpd_system *s) {
+    if (!s) return fail(DPD_EINVAL, "null system");
+    if (s->sticky != DPD_OK) return fail(s->sticky, "%s", s->sticky_msg.c_str());
+    return DPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpd_version(void) { return DPD_ABI_VERSION; }
+
+const char *dpd_last_error(void) { return g_err.c_str(); }
+
+int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos,
+               const double *vel, const uint8_t *type, int ntypes, uint64_t seed, int precision,
+               void *hip_stream, int cell_capacity) {
+    g_err.clear();
+    if (!out || !L || !pos || !vel) return fail(DPD_EINVAL, "null argument");
+    *out = nullptr;
+    if (n < 2) return fail(DPD_EINVAL, "need at least 2 particles, got %lld", (long long)n);
+    if (n >= (int64_t)0xFFFFFFFF) return fail(DPD_EINVAL, "too many particles");
+    if (precision != DPD_PREC_FP64 && precision != DPD_PREC_MIXED)
+        return fail(DPD_EINVAL, "unknown precision %d", precision);
+    if (ntypes < 1 || ntypes > 16) return fail(DPD_EINVAL, "ntypes must be in 1..16");
+    if (cell_capacity < 0 || cell_capacity > 1024)
+        return fail(DPD_EINVAL, "cell_capacity must be in 0..1024");
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(L[k])) return fail(DPD_EINVAL, "non-finite box");
+        if (L[k] < 3.0) return fail(DPD_EBOX, "box edge %g is below 3 cutoffs", L[k]);
+    }
+    if (!all_finite(pos, 3 * n) || !all_finite(vel, 3 * n))
+        return fail(DPD_EINVAL, "non-finite position or velocity");
+    if (type)
+        for (int64_t i = 0; i < n; ++i)
+            if (type[i] >= ntypes) return fail(DPD_EINVAL, "type %d of particle %lld >= ntypes",
+                                               (int)type[i], (long long)i);
+
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(DPD_EDEVICE, "device %s is not gfx950", prop.gcnArchName);
+
+    dpd_system *s = new (std::nothrow) dpd_system();
+    if (!s) return fail(DPD_ENOMEM, "host allocation failed");
+    s->prec = precision;
+    s->n = n;
+    s->ntypes = ntypes;
+    s->seed = seed;
+    s->cap = cell_capacity ? cell_capacity : 32;
+    for (int k = 0; k < 3; ++k) {
+        s->L[k] = L[k];
+        s->nc[k] = (int)std::floor(L[k]);
+        s->h[k] = L[k] / (double)s->nc[k];
+    }
+    s->ncells = (int64_t)s->nc[0] * s->nc[1] * s->nc[2];
+    if (s->ncells * (int64_t)s->cap >= (int64_t)0xFFFFFFFF) {
+        delete s;
+        return fail(DPD_EINVAL, "cells x capacity exceeds 32-bit slot indices");
+    }
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(DPD_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+        }
+        s->own_stream = true;
+    }
+    const size_t psz = precision == DPD_PREC_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>);
+    const size_t ssz = precision == DPD_PREC_FP64 ? sizeof(SRec<double>) : sizeof(SRec<float>);
+    const size_t slots = (size_t)s->ncells * s->cap;
+    int rc = DPD_OK;
+    for (int k = 0; k < 2 && !rc; ++k) {
+        rc = dmalloc(s, &s->P[k], slots * psz);
+        if (!rc) rc = dmalloc(s, &s->S[k], slots * ssz);
+        if (!rc) rc = dmalloc(s, (void **)&s->slot_of_tag[k], n * sizeof(uint32_t));
+    }
+    for (int k = 0; k < 3 && !rc; ++k)
+        rc = dmalloc(s, (void **)&s->count[k], s->ncells * sizeof(uint32_t));
+    if (!rc) rc = dmalloc(s, &s->a_dev, 256 * sizeof(double));
+    if (!rc) rc = dmalloc(s, (void **)&s->err, sizeof(uint32_t));
+    if (!rc) rc = dmalloc(s, (void **)&s->stage, 9 * n * sizeof(double));
+    if (!rc) rc = dmalloc(s, (void **)&s->cell_stage, n * sizeof(int64_t));
+    if (!rc) rc = dmalloc(s, (void **)&s->type_dev, n);
+    if (!rc) rc = dmalloc(s, (void **)&s->obs, 9 * n * sizeof(double));
+    if (!rc) rc = dmalloc(s, (void **)&s->obs_np, n * sizeof(uint32_t));
+    if (!rc) rc = dmalloc(s, (void **)&s->obs_ptrs, 8 * sizeof(double *));
+    s->red_blocks = (int)std::min<int64_t>(256, (n + 1023) / 1024);
+    if (!rc) rc = dmalloc(s, (void **)&s->red, (size_t)s->red_blocks * 8 * sizeof(double));
+    if (rc) {
+        free_all(s);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return rc;
+    }
+    auto setup = [&]() -> int {
+        HIP_OK(hipMemsetAsync(s->err, 0, sizeof(uint32_t), s->stream));
+        for (int k = 0; k < 2; ++k)
+            HIP_OK(launch_fill_u32(s->slot_of_tag[k], n, 0u, s->stream));
+        std::vector<uint8_t> tv(n, 0);
+        if (type) std::memcpy(tv.data(), type, n);
+        HIP_OK(hipMemcpyAsync(s->type_dev, tv.data(), n, hipMemcpyHostToDevice, s->stream));
+        double *ptrs[8] = {s->obs, s->obs + n, s->obs + 2 * n, s->obs + 3 * n, s->obs + 4 * n,
+                           s->obs + 5 * n, s->obs + 6 * n, s->obs + 7 * n};
+        HIP_OK(hipMemcpyAsync(s->obs_ptrs, ptrs, sizeof ptrs, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
+        return load_state(s, pos, vel, nullptr, 0);
+    };
+    rc = setup();
+    if (rc == DPD_OK) rc = check_device(s);
+    if (rc) {
+        std::string msg = g_err;
+        free_all(s);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return fail(rc, "%s", msg.c_str());
+    }
+    // Default brick: the largest one that still gives every CU work.
+    const int64_t cells = s->ncells;
+    s->variant = cells >= 64 * 1024 ? 0 : (cells >= 8 * 1024 ? 1 : 2);
+    *out = s;
+    return DPD_OK;
+}
+
+int dpd_set_params(dpd_system *s, const double *a_ij, double gamma, double sigma, double kT,
+                   double dt, double lambda) {
+    if (int rc = check_usable(s)) return rc;
+    if (s->frozen) return fail(DPD_ESTATE, "parameters are frozen after the first step");
+    if (!a_ij) return fail(DPD_EINVAL, "null a_ij");
+    const int m = s->ntypes;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            if (!std::isfinite(a_ij[i * m + j])) return fail(DPD_EINVAL, "non-finite a_ij");
+            if (a_ij[i * m + j] != a_ij[j * m + i]) return fail(DPD_EINVAL, "a_ij not symmetric");
+        }
+    if (!(gamma >= 0) || !(sigma >= 0) || !std::isfinite(gamma) || !std::isfinite(sigma))
+        return fail(DPD_EINVAL, "gamma and sigma must be finite and >= 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(DPD_EINVAL, "dt must be > 0");
+    if (!(lambda >= 0 && lambda <= 1)) return fail(DPD_EINVAL, "lambda must be in [0, 1]");
+    if (!std::isfinite(kT)) return fail(DPD_EINVAL, "non-finite kT");
+    s->a.assign(a_ij, a_ij + m * m);
+    s->gamma = gamma;
+    s->sigma = sigma;
+    s->kT = kT;
+    s->dt = dt;
+    s->lambda = lambda;
+    s->params_set = true;
+    return DPD_OK;
+}
+
+int dpd_add_bonds(dpd_system *s, int64_t nb, const int32_t *btype, const int64_t *i,
+                  const int64_t *j, const double *r_e, const double *k, const double *alpha) {
+    if (int rc = check_usable(s)) return rc;
+    if (s->frozen) return fail(DPD_ESTATE, "bonds are frozen after the first step");
+    if (nb < 0) return fail(DPD_EINVAL, "negative bond count");
+    if (nb == 0) return DPD_OK;
+    if (!btype || !i || !j || !r_e || !k || !alpha) return fail(DPD_EINVAL, "null bond array");
+    // Validate against the current positions (minimum image needs r < L/2).
+    std::vector<double> x(3 * s->n);
+    HIP_OK(hipStreamSynchronize(s->stream));
+    if (int rc = dpd_get_state(s, x.data(), nullptr, nullptr, nullptr)) return rc;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (btype[b] < DPD_BOND_HARMONIC || btype[b] > DPD_BOND_MORSE)
+            return fail(DPD_EINVAL, "bond %lld: unknown type %d", (long long)b, btype[b]);
+        if (i[b] < 0 || j[b] < 0 || i[b] >= s->n || j[b] >= s->n || i[b] == j[b])
+            return fail(DPD_ERANGE, "bond %lld: bad tags (%lld, %lld)", (long long)b,
+                        (long long)i[b], (long long)j[b]);
+        if (!std::isfinite(r_e[b]) || !std::isfinite(k[b]) || !std::isfinite(alpha[b]))
+            return fail(DPD_EINVAL, "bond %lld: non-finite parameter", (long long)b);
+        for (int c = 0; c < 3; ++c) {
+            double d = x[3 * i[b] + c] - x[3 * j[b] + c];
+            d -= s->L[c] * std::nearbyint(d / s->L[c]);
+            if (std::fabs(d) >= 0.5 * s->L[c] - 1e-12)
+                return fail(DPD_ERANGE, "bond %lld spans half the box", (long long)b);
+        }
+    }
+    s->btype.insert(s->btype.end(), btype, btype + nb);
+    s->bi.insert(s->bi.end(), i, i + nb);
+    s->bj.insert(s->bj.end(), j, j + nb);
+    s->bre.insert(s->bre.end(), r_e, r_e + nb);
+    s->bk.insert(s->bk.end(), k, k + nb);
+    s->balpha.insert(s->balpha.end(), alpha, alpha + nb);
+    return DPD_OK;
+}
+
+static int step_impl(dpd_system *s, int64_t nsteps, dpd_kernel_times *tm) {
+    if (int rc = check_usable(s)) return rc;
+    if (nsteps < 0) return fail(DPD_EINVAL, "negative step count");
+    if (nsteps == 0) return DPD_OK;
+    if (int rc = freeze(s)) return rc;
+    if (int rc = ensure_force(s)) return rc;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (tm) {
+        std::memset(tm, 0, sizeof *tm);
+        HIP_OK(hipEventCreate(&ev[0]));
+        HIP_OK(hipEventCreate(&ev[1]));
+    }
+    auto timed = [&](auto &&fn, double *acc, int64_t *cnt) -> int {
+        if (tm) HIP_OK(hipEventRecord(ev[0], s->stream));
+        if (int rc = fn()) return rc;
+        if (tm) {
+            HIP_OK(hipEventRecord(ev[1], s->stream));
+            HIP_OK(hipEventSynchronize(ev[1]));
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            *acc += ms;
+            ++*cnt;
+        }
+        return DPD_OK;
+    };
+    const uint32_t t0 = (uint32_t)s->t;
+    int rc = timed([&] { return begin(s, t0); }, tm ? &tm->ms_begin : nullptr,
+                   tm ? &tm->n_begin : nullptr);
+    for (int64_t k = 1; k < nsteps && !rc; ++k)
+        rc = timed([&] { return force(s, t0 + (uint32_t)k, FORCE_FUSED); },
+                   tm ? &tm->ms_fused : nullptr, tm ? &tm->n_fused : nullptr);
+    if (!rc)
+        rc = timed([&] { return force(s, t0 + (uint32_t)nsteps, FORCE_FINISH); },
+                   tm ? &tm->ms_finish : nullptr, tm ? &tm->n_finish : nullptr);
+    if (tm) {
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
+    if (rc) return rc;
+    s->t += nsteps;
+    if (tm) return check_device(s);
+    return DPD_OK;
+}
+
+int dpd_step(dpd_system *s, int64_t nsteps) { return step_impl(s, nsteps, nullptr); }
+
+int dpd_step_profiled(dpd_system *s, int64_t nsteps, dpd_kernel_times *out) {
+    if (!out) return fail(DPD_EINVAL, "null timing output");
+    return step_impl(s, nsteps, out);
+}
+
+int dpd_sync(dpd_system *s) {
+    if (!s) return fail(DPD_EINVAL, "null system");
+    return check_device(s);
+}
+
+int dpd_get_state(dpd_system *s, double *pos, double *vel, double *frc, int64_t *step) {
+    if (int rc = check_usable(s)) return rc;
+    if (frc) {
+        // The force needs the parameters and the bond list, which freezes them.
+        if (int rc = freeze(s)) return rc;
+        if (int rc = ensure_force(s)) return rc;
+    }
+    const int64_t n = s->n;
+    const uint32_t q = (uint32_t)s->t;
+    if (s->prec == DPD_PREC_FP64)
+        HIP_OK(launch_gather<double>(make_dev<double>(s), q, s->stage, s->stage + 3 * n,
+                                     s->stage + 6 * n, s->cell_stage, s->stream));
+    else
+        HIP_OK(launch_gather<float>(make_dev<float>(s), q, s->stage, s->stage + 3 * n,
+                                    s->stage + 6 * n, s->cell_stage, s->stream));
+    if (int rc = check_device(s)) return rc;
+    if (pos) HIP_OK(hipMemcpy(pos, s->stage, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (vel)
+        HIP_OK(hipMemcpy(vel, s->stage + 3 * n, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (frc) {
+        HIP_OK(hipMemcpy(frc, s->stage + 6 * n, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if (step) *step = s->t;
+    return DPD_OK;
+}
+
+int dpd_set_state(dpd_system *s, const double *pos, const double *vel, const double *frc,
+                  int64_t step) {
+    if (int rc = check_usable(s)) return rc;
+    if (!pos || !vel) return fail(DPD_EINVAL, "null position or velocity");
+    if (step < 0) return fail(DPD_EINVAL, "negative step counter");
+    if (!all_finite(pos, 3 * s->n) || !all_finite(vel, 3 * s->n) ||
+        (frc && !all_finite(frc, 3 * s->n)))
+        return fail(DPD_EINVAL, "non-finite state");
+    if (int rc = load_state(s, pos, vel, frc, step)) return rc;
+    return check_device(s);
+}
+
+int dpd_get_cells(dpd_system *s, int64_t *cell_of_tag, int64_t *count) {
+    if (int rc = check_usable(s)) return rc;
+    const int64_t n = s->n;
+    const uint32_t q = (uint32_t)s->t;
+    if (s->prec == DPD_PREC_FP64)
+        HIP_OK(launch_gather<double>(make_dev<double>(s), q, s->stage, s->stage + 3 * n,
+                                     s->stage + 6 * n, s->cell_stage, s->stream));
+    else
+        HIP_OK(launch_gather<float>(make_dev<float>(s), q, s->stage, s->stage + 3 * n,
+                                    s->stage + 6 * n, s->cell_stage, s->stream));
+    if (int rc = check_device(s)) return rc;
+    if (cell_of_tag)
+        HIP_OK(hipMemcpy(cell_of_tag, s->cell_stage, n * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (count) {
+        std::vector<uint32_t> c(s->ncells);
+        HIP_OK(hipMemcpy(c.data(), s->count[s->t % 3], s->ncells * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost));
+        for (int64_t g = 0; g < s->ncells; ++g) count[g] = c[g];
+    }
+    return DPD_OK;
+}
+
+int dpd_observables(dpd_system *s, dpd_obs *out) {
+    if (int rc = check_usable(s)) return rc;
+    if (!out) return fail(DPD_EINVAL, "null output");
+    if (int rc = freeze(s)) return rc;
+    const int64_t n = s->n;
+    if (int rc = force(s, (uint32_t)s->t, FORCE_OBS)) return rc;
+    HIP_OK(launch_u32_to_f64(s->obs_np, s->obs + 5 * n, n, s->stream));
+    const int64_t chunk = (n + s->red_blocks - 1) / s->red_blocks;
+    HIP_OK(launch_reduce8((const double *const *)s->obs_ptrs, n, chunk, s->red_blocks, s->red,
+                          s->stream));
+    if (int rc = check_device(s)) return rc;
+    std::vector<double> part((size_t)s->red_blocks * 8);
+    HIP_OK(hipMemcpy(part.data(), s->red, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < s->red_blocks; ++b)
+        for (int k = 0; k < 8; ++k) tot[k] += part[(size_t)b * 8 + k];
+    // obs layout: u, w, ub, wb, ke, npairs, px.. (interleaved 3n at 6n: summed as 2 arrays)
+    out->step = s->t;
+    out->time = (double)s->t * s->dt;
+    out->u_pair = tot[0];
+    out->w_pair = tot[1];
+    out->u_bond = tot[2];
+    out->w_bond = tot[3];
+    out->ke = tot[4];
+    out->npairs = (int64_t)std::llround(0.5 * tot[5]);
+    out->kT = 2.0 * out->ke / (3.0 * (double)n - 3.0);
+    const double V = s->L[0] * s->L[1] * s->L[2];
+    out->pressure = (2.0 * out->ke + out->w_pair + out->w_bond) / (3.0 * V);
+    // Momentum: per-tag (px, py, pz) interleaved over [6n, 9n).
+    std::vector<double> p(3 * n);
+    HIP_OK(hipMemcpy(p.data(), s->obs + 6 * n, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+    double P[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) P[c] += p[3 * i + c];
+    for (int c = 0; c < 3; ++c) out->momentum[c] = P[c];
+    return DPD_OK;
+}
+
+int dpd_info(dpd_system *s, int64_t out[8]) {
+    if (!s || !out) return fail(DPD_EINVAL, "null argument");
+    out[0] = s->n;
+    out[1] = s->ncells;
+    out[2] = s->cap;
+    out[3] = (int64_t)s->bytes;
+    out[4] = s->nc[0];
+    out[5] = s->nc[1];
+    out[6] = s->nc[2];
+    out[7] = s->prec;
+    return DPD_OK;
+}
+
+void dpd_destroy(dpd_system *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_all(s);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+// Device-side building blocks of the DPD step for gfx950: records, the pair
+// noise, binning and the pair / bond force terms.
+//
+// Method: Groot-style DPD as defined by Doi et al. (arXiv 1804.06205):
+// Eq. (3) total force, Eq. (4) conservative repulsion, the Groot-Warren
+// dissipative and random forces named after Eq. (5), bonds of Eqs. (6)-(8)
+// and Fig. 3a, and the modified velocity Verlet of Fig. 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpd {
+
+// ---------------------------------------------------------------------------
+// Records kept per cell slot.  A cell owns `cap` consecutive slots; the first
+// count[cell] of them are occupied, in arbitrary order (binning appends with
+// atomics); kernels restore ascending tag order where summation order matters.
+// ---------------------------------------------------------------------------
+
+// Pair record: what a neighbour needs (position relative to its cell's origin,
+// predicted velocity vt, tag, type).
+template <typename T> struct PRec;
+template <> struct alignas(16) PRec<float> {
+    float ox, oy, oz;
+    uint32_t tag;
+    float vx, vy, vz;
+    uint32_t type;
+};
+template <> struct alignas(16) PRec<double> {
+    double ox, oy, oz;
+    double vx, vy, vz;
+    uint32_t tag, type;
+    uint64_t pad;
+};
+
+// State record: FP64 position, velocity and force of the particle itself.
+template <typename T> struct SRec;
+template <> struct alignas(16) SRec<float> {
+    double x, y, z;
+    float vx, vy, vz;
+    float fx, fy, fz;
+};
+template <> struct alignas(16) SRec<double> {
+    double x, y, z;
+    double vx, vy, vz;
+    double fx, fy, fz;
+    double pad;
+};
+
+// One end of a bond record, stored with the particle that owns it.
+template <typename T> struct BondEnt {
+    uint32_t partner;   // tag of the other end
+    int32_t type;       // 1 harmonic, 2 paper Morse, 3 standard Morse
+    T r_e, k, alpha;
+};
+
+// Sticky device error bits.
+enum : uint32_t {
+    ERR_CELL_OVERFLOW = 1u,    // a cell got more than `cap` particles
+    ERR_TILE_OVERFLOW = 2u,    // a brick's neighbourhood exceeded the tile buffer
+    ERR_NONFINITE = 4u,        // non-finite position, velocity or force
+    ERR_DISPLACEMENT = 8u,     // a step moved a particle by more than half a box
+    ERR_INDEX = 16u            // an index outside its array (internal consistency)
+};
+
+// Everything a kernel needs about one system.  Passed by value.
+template <typename T> struct DevSys {
+    double L[3];        // box edges
+    double h[3];        // cell edges, L / nc
+    int nc[3];          // cells per axis
+    int cap;            // slots per cell
+    int64_t ncells;
+    int64_t n;
+    int ntypes;
+    T dt, lambda, gamma, sigma_rdt;   // sigma_rdt = sigma / sqrt(dt)
+    double dt_d, half_dt2_d;          // FP64 copies for the position update
+    uint64_t seed;
+    const T *a;                       // ntypes x ntypes repulsion table
+    PRec<T> *P[2];                    // layouts, indexed by state parity
+    SRec<T> *S[2];
+    uint32_t *slot_of_tag[2];
+    uint32_t *count[3];               // cell counts, indexed by state mod 3
+    const uint32_t *bond_off;         // CSR over tags (n + 1) or null
+    const BondEnt<T> *bonds;
+    uint32_t *err;
+    // Per-tag observables scratch (written by the observables pass).
+    double *obs_u, *obs_w, *obs_ub, *obs_wb, *obs_ke, *obs_p;
+    uint32_t *obs_np;
+};
+
+// Precision-generic math wrappers (float calls the f-suffixed functions).
+__device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float t_exp(float x) { return expf(x); }
+__device__ __forceinline__ double t_exp(double x) { return exp(x); }
+__device__ __forceinline__ float t_abs(float x) { return fabsf(x); }
+__device__ __forceinline__ double t_abs(double x) { return fabs(x); }
+
+// ---------------------------------------------------------------------------
+// Pair noise: Philox4x32-10 keyed by the seed, counter (min tag, max tag, s,
+// 0), then Box-Muller on the first two words.
+// ---------------------------------------------------------------------------
+
+// 32x32 -> 64 product split into (hi, lo).
+__device__ __forceinline__ void mulhilo(uint32_t a, uint32_t b, uint32_t &hi, uint32_t &lo) {
+    const uint64_t p = (uint64_t)a * (uint64_t)b;
+    hi = (uint32_t)(p >> 32);
+    lo = (uint32_t)p;
+}
+
+// Returns the first two output words of Philox4x32 with ten rounds.
+__device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                           uint32_t k0, uint32_t k1, uint32_t &w0,
+                                           uint32_t &w1) {
+    constexpr uint32_t MA = 0xD2511F53u, MB = 0xCD9E8D57u;
+    constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hA, lA, hB, lB;
+        mulhilo(MA, c0, hA, lA);
+        mulhilo(MB, c2, hB, lB);
+        const uint32_t n0 = hB ^ c1 ^ k0;
+        const uint32_t n2 = hA ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lB;
+        c2 = n2;
+        c3 = lA;
+        k0 += WA;
+        k1 += WB;
+    }
+    w0 = c0;
+    w1 = c1;
+}
+
+template <typename T> __device__ __forceinline__ T box_muller(uint32_t w0, uint32_t w1);
+
+template <> __device__ __forceinline__ float box_muller<float>(uint32_t w0, uint32_t w1) {
+    const float u1 = (float)((w0 >> 8) + 1u) * 0x1.0p-24f;   // (0, 1]
+    const float u2 = (float)(w1 >> 8) * 0x1.0p-24f;          // [0, 1)
+    return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+template <> __device__ __forceinline__ double box_muller<double>(uint32_t w0, uint32_t w1) {
+    const double u1 = (double)((w0 >> 8) + 1u) * 0x1.0p-24;
+    const double u2 = (double)(w1 >> 8) * 0x1.0p-24;
+    return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+template <typename T>
+__device__ __forceinline__ T pair_theta(uint64_t seed, uint32_t ti, uint32_t tj, uint32_t s) {
+    const uint32_t lo = min(ti, tj), hi = max(ti, tj);
+    uint32_t w0, w1;
+    philox_w01(lo, hi, s, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), w0, w1);
+    return box_muller<T>(w0, w1);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry.
+// ---------------------------------------------------------------------------
+
+// Periodic wrap of one coordinate: one shift, and a value that rounds onto L
+// after the upward shift becomes 0.
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+    if (x < 0.0) x += L;
+    else if (x >= L) x -= L;
+    if (x >= L) x = 0.0;
+    return x;
+}
+
+// Cell coordinate floor(x / h) with an IEEE FP64 divide, clamped to [0, n-1].
+__device__ __forceinline__ int cell_coord(double x, double h, int n) {
+    int c = (int)floor(__ddiv_rn(x, h));
+    c = c > n - 1 ? n - 1 : c;
+    c = c < 0 ? 0 : c;
+    return c;
+}
+
+__device__ __forceinline__ int64_t cell_linear(int cx, int cy, int cz, const int nc[3]) {
+    return ((int64_t)cz * nc[1] + cy) * nc[0] + cx;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+    return d - L * rint(d / L);
+}
+
+// ---------------------------------------------------------------------------
+// Bond term (Eqs. 6-8, Fig. 3a).  d = x_i - x_j (minimum image).  Returns
+// the coefficient c with F_i = c d; energy and virial through u, w.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T bond_coef(int type, T r2, T r_e, T k, T alpha, T &u, T &w) {
+    const T r = t_sqrt(r2);
+    T c = (T)0;
+    if (type == 1) {
+        const T x = r - r_e;
+        if (r_e == (T)0) c = -k;
+        else if (r > (T)0) c = -k * x / r;
+        u = (T)0.5 * k * x * x;
+    } else if (type == 2) {
+        const T E = t_exp(-alpha * t_abs(r - r_e));
+        if (r > (T)0) c = (T)-2 * alpha * k * E * ((T)1 - E) / r;
+        u = k * ((T)1 - E) * ((T)1 - E);
+    } else {
+        const T E = t_exp(-alpha * (r - r_e));
+        if (r > (T)0) c = (T)-2 * alpha * k * E * ((T)1 - E) / r;
+        u = k * (((T)1 - E) * ((T)1 - E) - (T)1);
+    }
+    w = c * r2;
+    return c;
+}
+
+}  // namespace dpd

@@ -1,0 +1,690 @@
+// HIP kernels of the DPD step for gfx950 (CDNA4, 64-wide waves).
+//
+// One step of Fig. 1 (Groot's modified velocity Verlet) is split as
+//   begin   : resting state q -> integrate-1 (drift, wrap, predictor) and
+//             binning into the layout of state q+1;
+//   fused   : forces of state q (pair sum over the 27 cells around each cell,
+//             the design section's cell list with no neighbour list, plus
+//             bonds), integrate-2 (Fig. 1 step 5), then integrate-1 and
+//             binning of state q+1, all in one pass over the particles;
+//   finish  : forces of state q and integrate-2, in place.
+// dpd_step(n) runs begin, n-1 fused passes and one finish.
+//
+// Layouts.  Each state lives in a padded cell layout: cell g owns slots
+// [g cap, (g+1) cap); count[g] of them are filled, in arbitrary order, by
+// atomic appends.  Two layouts (state parity) and three count arrays (state
+// mod 3) rotate, so a kernel reads one layout and writes the other while it
+// zeroes the counts two states ahead.  Pair kernels restore ascending tag
+// order inside each cell when they stage a neighbourhood in LDS, so every
+// particle sums its pair forces in the same order on every run, whatever the
+// storage order, and results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dpd_device.hpp"
+#include "dpd_kernels.hpp"
+
+namespace dpd {
+
+constexpr int QCAP = 8;          // per-lane pending-pair queue depth
+constexpr int MAXTYPES = 16;
+
+enum : int { MODE_INIT = 0, MODE_FINISH = 1, MODE_FUSED = 2, MODE_OBS = 3 };
+
+// Neighbour data staged in LDS.
+template <typename T> struct alignas(16) LA { T ox, oy, oz; uint32_t tag; };
+template <typename T> struct alignas(16) LB { T vx, vy, vz; uint32_t type; };
+
+__device__ __forceinline__ int wrapi(int c, int n) {
+    c = c < 0 ? c + n : c;
+    return c >= n ? c - n : c;
+}
+
+// Maximum of v over the wave.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Exclusive prefix sum of a[0..m) in place (m <= NT * IPT), a[m] = total.
+// All threads of the block must call it.
+template <int NT, int IPT>
+__device__ void block_scan(int *a, int m, int *s_wave) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    int v[IPT];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int idx = tid * IPT + k;
+        v[k] = idx < m ? a[idx] : 0;
+        sum += v[k];
+    }
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) s_wave[wid] = incl;
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wid; ++w) wbase += s_wave[w];
+    int run = wbase + incl - sum;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int idx = tid * IPT + k;
+        if (idx < m) a[idx] = run;
+        run += v[k];
+    }
+    if (tid == NT - 1) a[m] = run;
+    __syncthreads();
+}
+
+// Largest index c in [0, m) with a[c] <= u, for a non-decreasing a.
+__device__ __forceinline__ int find_bin(const int *a, int m, int u) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Work-group -> brick map that gives each XCD a contiguous range of bricks
+// (work-groups are dealt to the 8 XCDs round robin), so the neighbourhood
+// re-reads of adjacent bricks hit the same L2.
+__device__ __forceinline__ int xcd_brick(int bid, int nb) {
+    const int x = bid & 7, k = bid >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return x * per + min(x, rem) + k;
+}
+
+// Integrate-1 (Fig. 1 steps 1-2) of one particle and its append to the
+// layout of the next state.  Shared by begin and fused so both round alike.
+template <typename T>
+__device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, double x,
+                                              double y, double z, T vx, T vy, T vz, T fx,
+                                              T fy, T fz, uint32_t tag, uint32_t type) {
+    const double dx = D.dt_d * (double)vx + D.half_dt2_d * (double)fx;
+    const double dy = D.dt_d * (double)vy + D.half_dt2_d * (double)fy;
+    const double dz = D.dt_d * (double)vz + D.half_dt2_d * (double)fz;
+    if (!(fabs(dx) <= 0.5 * D.L[0] && fabs(dy) <= 0.5 * D.L[1] && fabs(dz) <= 0.5 * D.L[2])) {
+        atomicOr(D.err, (isfinite(dx) && isfinite(dy) && isfinite(dz)) ? ERR_DISPLACEMENT
+                                                                       : ERR_NONFINITE);
+        return;
+    }
+    x = wrap_coord(x + dx, D.L[0]);
+    y = wrap_coord(y + dy, D.L[1]);
+    z = wrap_coord(z + dz, D.L[2]);
+    const T lt = D.lambda * D.dt;
+    const T tx = vx + lt * fx, ty = vy + lt * fy, tz = vz + lt * fz;
+    const int cx = cell_coord(x, D.h[0], D.nc[0]);
+    const int cy = cell_coord(y, D.h[1], D.nc[1]);
+    const int cz = cell_coord(z, D.h[2], D.nc[2]);
+    const int64_t g = cell_linear(cx, cy, cz, D.nc);
+    const uint32_t k = atomicAdd(&D.count[qn % 3u][g], 1u);
+    if (k >= (uint32_t)D.cap) {
+        atomicOr(D.err, ERR_CELL_OVERFLOW);
+        return;
+    }
+    const int64_t slot = g * D.cap + k;
+    const uint32_t ln = qn & 1u;
+    PRec<T> p;
+    p.ox = (T)(x - (double)cx * D.h[0]);
+    p.oy = (T)(y - (double)cy * D.h[1]);
+    p.oz = (T)(z - (double)cz * D.h[2]);
+    p.tag = tag;
+    p.vx = tx;
+    p.vy = ty;
+    p.vz = tz;
+    p.type = type;
+    D.P[ln][slot] = p;
+    SRec<T> s;
+    s.x = x;
+    s.y = y;
+    s.z = z;
+    s.vx = vx;
+    s.vy = vy;
+    s.vz = vz;
+    s.fx = fx;
+    s.fy = fy;
+    s.fz = fz;
+    D.S[ln][slot] = s;
+    D.slot_of_tag[ln][tag] = (uint32_t)slot;
+}
+
+// ---------------------------------------------------------------------------
+// Pair + bond force over one brick of BX x BY x BZ cells.
+// ---------------------------------------------------------------------------
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE>
+__global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, int nby,
+                                              int nbricks) {
+    constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
+    constexpr int NHC = HX * HY * HZ;
+    constexpr int NOC = BX * BY * BZ;
+    constexpr int RPT = (HCAP + NT - 1) / NT;
+    constexpr int IPT_H = (NHC + 1 + NT - 1) / NT;
+    constexpr int IPT_O = (NOC + 1 + NT - 1) / NT;
+    static_assert(QCAP * NT >= HCAP, "queue area doubles as the tag scratch");
+
+    __shared__ int s_hcell[NHC];
+    __shared__ int s_hstart[NHC + 1];
+    __shared__ int s_ostart[NOC + 1];
+    __shared__ int s_wave[NT / 64];
+    __shared__ int s_flag;
+    __shared__ T s_a[MAXTYPES * MAXTYPES];
+    __shared__ LA<T> s_A[HCAP];
+    __shared__ LB<T> s_B[HCAP];
+    __shared__ uint32_t s_q[QCAP * NT];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const uint32_t lay = q & 1u;
+    const uint32_t *cnt = D.count[q % 3u];
+    const int cap = D.cap;
+
+    if (tid == 0) s_flag = (int)*D.err;
+    __syncthreads();
+    if (s_flag) return;
+
+    const int b = xcd_brick(blockIdx.x, nbricks);
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int c0x = bx * BX, c0y = by * BY, c0z = bz * BZ;
+    const int ex = min(BX, D.nc[0] - c0x), ey = min(BY, D.nc[1] - c0y), ez = min(BZ, D.nc[2] - c0z);
+
+    // Halo cells (own cells plus one layer, periodic) and their counts.
+    for (int hc = tid; hc < NHC; hc += NT) {
+        const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+        int g = -1, c = 0;
+        if (hx <= ex + 1 && hy <= ey + 1 && hz <= ez + 1) {
+            const int gx = wrapi(c0x + hx - 1, D.nc[0]);
+            const int gy = wrapi(c0y + hy - 1, D.nc[1]);
+            const int gz = wrapi(c0z + hz - 1, D.nc[2]);
+            g = (int)cell_linear(gx, gy, gz, D.nc);
+            c = (int)cnt[g];
+            if (c > cap) {
+                atomicOr(D.err, ERR_INDEX);
+                c = cap;
+            }
+        }
+        s_hcell[hc] = g;
+        s_hstart[hc] = c;
+    }
+    for (int i = tid; i < D.ntypes * D.ntypes; i += NT) s_a[i] = D.a[i];
+    if (MODE == MODE_FUSED) {
+        // Counts of state q+2 were last read for state q-1; clear this brick's.
+        uint32_t *cz2 = D.count[(q + 2u) % 3u];
+        for (int oc = tid; oc < NOC; oc += NT) {
+            const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
+            if (ox < ex && oy < ey && oz < ez)
+                cz2[cell_linear(c0x + ox, c0y + oy, c0z + oz, D.nc)] = 0u;
+        }
+    }
+    __syncthreads();
+    block_scan<NT, IPT_H>(s_hstart, NHC, s_wave);
+    for (int oc = tid; oc < NOC; oc += NT) {
+        const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
+        int c = 0;
+        if (ox < ex && oy < ey && oz < ez) {
+            const int hc = ((oz + 1) * HY + (oy + 1)) * HX + (ox + 1);
+            c = s_hstart[hc + 1] - s_hstart[hc];
+        }
+        s_ostart[oc] = c;
+    }
+    __syncthreads();
+    block_scan<NT, IPT_O>(s_ostart, NOC, s_wave);
+    const int ntot = s_hstart[NHC];
+    const int nown = s_ostart[NOC];
+    if (ntot > HCAP) {
+        if (tid == 0) atomicOr(D.err, ERR_TILE_OVERFLOW);
+        return;
+    }
+
+    // Stage the neighbourhood in LDS, ascending tag order inside each cell.
+    {
+        PRec<T> rec[RPT];
+        int hcs[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int u = tid + r * NT;
+            hcs[r] = -1;
+            if (u < ntot) {
+                const int hc = find_bin(s_hstart, NHC, u);
+                hcs[r] = hc;
+                rec[r] = D.P[lay][(int64_t)s_hcell[hc] * cap + (u - s_hstart[hc])];
+                s_q[u] = rec[r].tag;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if (hcs[r] >= 0) {
+                const int lo = s_hstart[hcs[r]], hi = s_hstart[hcs[r] + 1];
+                int rank = 0;
+                for (int v = lo; v < hi; ++v) rank += s_q[v] < rec[r].tag ? 1 : 0;
+                const int d = lo + rank;
+                LA<T> a;
+                a.ox = rec[r].ox;
+                a.oy = rec[r].oy;
+                a.oz = rec[r].oz;
+                a.tag = rec[r].tag;
+                LB<T> bb;
+                bb.vx = rec[r].vx;
+                bb.vy = rec[r].vy;
+                bb.vz = rec[r].vz;
+                bb.type = rec[r].type;
+                s_A[d] = a;
+                s_B[d] = bb;
+            }
+        }
+        __syncthreads();
+    }
+
+    const T hxT = (T)D.h[0], hyT = (T)D.h[1], hzT = (T)D.h[2];
+    (void)lane;
+    const T gamma = D.gamma, srdt = D.sigma_rdt;
+    const int ntypes = D.ntypes;
+    uint32_t *myq = s_q + tid;
+
+    for (int base = 0; base < nown; base += NT) {
+        const int qi = base + tid;
+        const bool have = qi < nown;
+        int oxc = 0, oyc = 0, ozc = 0;
+        int64_t slot = 0;
+        PRec<T> pi;
+        pi.ox = pi.oy = pi.oz = (T)0;
+        pi.vx = pi.vy = pi.vz = (T)0;
+        pi.tag = 0xFFFFFFFFu;
+        pi.type = 0;
+        if (have) {
+            const int oc = find_bin(s_ostart, NOC, qi);
+            oxc = oc % BX;
+            oyc = (oc / BX) % BY;
+            ozc = oc / (BX * BY);
+            const int hc = ((ozc + 1) * HY + (oyc + 1)) * HX + (oxc + 1);
+            slot = (int64_t)s_hcell[hc] * cap + (qi - s_ostart[oc]);
+            pi = D.P[lay][slot];
+        }
+        const T *arow = s_a + (int)pi.type * ntypes;
+        // Lanes with a particle; pending pairs are processed once 3/4 of them
+        // have one queued.
+        const int nact = __popcll(__ballot(have));
+        const int rth = max(1, (3 * nact) / 4);
+        T fx = 0, fy = 0, fz = 0;
+        double ou = 0.0, ow = 0.0;
+        uint32_t onp = 0;
+        uint32_t qh = 0, qt = 0;
+
+        // Pops one queued neighbour per lane that has one and adds its force.
+        auto process = [&]() {
+            if (qt != qh) {
+                const uint32_t e = myq[(qh % QCAP) * NT];
+                ++qh;
+                const int j = (int)(e & 0xFFFFu);
+                const int code = (int)(e >> 16);
+                const int sx = code % 3 - 1, sy = (code / 3) % 3 - 1, sz = code / 9 - 1;
+                const LA<T> a = s_A[j];
+                const LB<T> bj = s_B[j];
+                const T dx = (pi.ox - a.ox) - (T)sx * hxT;
+                const T dy = (pi.oy - a.oy) - (T)sy * hyT;
+                const T dz = (pi.oz - a.oz) - (T)sz * hzT;
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T aij = arow[bj.type];
+                if (MODE == MODE_OBS) {
+                    ++onp;
+                    if (r2 > (T)0) {
+                        const T r = t_sqrt(r2);
+                        const T w = (T)1 - r;
+                        ou += (double)(aij * w * w);
+                        ow += (double)(aij * w * r);
+                    }
+                } else if (r2 > (T)0) {
+                    const T r = t_sqrt(r2);
+                    const T rinv = (T)1 / r;
+                    const T w = (T)1 - r;
+                    const T edv = (dx * (pi.vx - bj.vx) + dy * (pi.vy - bj.vy) +
+                                   dz * (pi.vz - bj.vz)) * rinv;
+                    const T th = pair_theta<T>(D.seed, pi.tag, a.tag, q);
+                    const T c = (aij * w - gamma * w * w * edv + srdt * w * th) * rinv;
+                    fx += c * dx;
+                    fy += c * dy;
+                    fz += c * dz;
+                }
+            }
+        };
+
+        for (int row = 0; row < 9; ++row) {
+            const int dyc = row % 3 - 1, dzc = row / 3 - 1;
+            int jb = 0, b1 = 0, b2 = 0, je = 0;
+            if (have) {
+                const int hr = ((ozc + 1 + dzc) * HY + (oyc + 1 + dyc)) * HX + oxc;
+                jb = s_hstart[hr];
+                b1 = s_hstart[hr + 1];
+                b2 = s_hstart[hr + 2];
+                je = s_hstart[hr + 3];
+            }
+            const T syT = (T)dyc * hyT, szT = (T)dzc * hzT;
+            const int len = je - jb;
+            const int maxlen = wave_max(len);
+            const uint32_t rowcode = (uint32_t)(3 * (dyc + 1) + 9 * (dzc + 1));
+            for (int t = 0; t < maxlen; ++t) {
+                if (t < len) {
+                    const int j = jb + t;
+                    const LA<T> a = s_A[j];
+                    const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
+                    const T dx = (pi.ox - a.ox) - (T)sx * hxT;
+                    const T dy = (pi.oy - a.oy) - syT;
+                    const T dz = (pi.oz - a.oz) - szT;
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < (T)1 && a.tag != pi.tag) {
+                        myq[(qt % QCAP) * NT] = (uint32_t)j | ((rowcode + (uint32_t)(sx + 1)) << 16);
+                        ++qt;
+                    }
+                }
+                const uint64_t pend = __ballot(qt != qh);
+                const uint64_t full = __ballot(qt - qh == (uint32_t)QCAP);
+                if (__popcll(pend) >= rth || full) process();
+            }
+        }
+        while (__ballot(qt != qh)) process();
+
+        if (!have) continue;
+
+        // Bonds (Eq. 8): every record owned by this particle, in input order.
+        const SRec<T> si = D.S[lay][slot];
+        double oub = 0.0, owb = 0.0;
+        if (D.bond_off) {
+            const uint32_t k0 = D.bond_off[pi.tag], k1 = D.bond_off[pi.tag + 1];
+            for (uint32_t k = k0; k < k1; ++k) {
+                const BondEnt<T> be = D.bonds[k];
+                uint32_t sj = D.slot_of_tag[lay][be.partner];
+                if ((int64_t)sj >= D.ncells * cap) {
+                    atomicOr(D.err, ERR_INDEX);
+                    sj = 0;
+                }
+                const SRec<T> &pj = D.S[lay][sj];
+                const T ddx = (T)min_image(si.x - pj.x, D.L[0]);
+                const T ddy = (T)min_image(si.y - pj.y, D.L[1]);
+                const T ddz = (T)min_image(si.z - pj.z, D.L[2]);
+                T u, w;
+                const T c = bond_coef<T>(be.type, ddx * ddx + ddy * ddy + ddz * ddz, be.r_e, be.k,
+                                         be.alpha, u, w);
+                fx += c * ddx;
+                fy += c * ddy;
+                fz += c * ddz;
+                oub += 0.5 * (double)u;
+                owb += 0.5 * (double)w;
+            }
+        }
+
+        if (MODE == MODE_OBS) {
+            const uint32_t tg = pi.tag;
+            D.obs_u[tg] = 0.25 * ou;
+            D.obs_w[tg] = 0.5 * ow;
+            D.obs_np[tg] = onp;
+            D.obs_ub[tg] = oub;
+            D.obs_wb[tg] = owb;
+            D.obs_ke[tg] = 0.5 * ((double)si.vx * si.vx + (double)si.vy * si.vy +
+                                  (double)si.vz * si.vz);
+            D.obs_p[3 * tg + 0] = (double)si.vx;
+            D.obs_p[3 * tg + 1] = (double)si.vy;
+            D.obs_p[3 * tg + 2] = (double)si.vz;
+            continue;
+        }
+        if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) atomicOr(D.err, ERR_NONFINITE);
+
+        SRec<T> *sp = &D.S[lay][slot];
+        if (MODE == MODE_INIT) {
+            sp->fx = fx;
+            sp->fy = fy;
+            sp->fz = fz;
+            continue;
+        }
+        // Integrate-2 (Fig. 1 step 5): v <- v + dt (f + f') / 2, f <- f'.
+        const T hdt = (T)0.5 * D.dt;
+        const T vx = si.vx + hdt * (si.fx + fx);
+        const T vy = si.vy + hdt * (si.fy + fy);
+        const T vz = si.vz + hdt * (si.fz + fz);
+        if (MODE == MODE_FINISH) {
+            sp->vx = vx;
+            sp->vy = vy;
+            sp->vz = vz;
+            sp->fx = fx;
+            sp->fy = fy;
+            sp->fz = fz;
+        } else {
+            drift_and_bin<T>(D, q + 1u, si.x, si.y, si.z, vx, vy, vz, fx, fy, fz, pi.tag, pi.type);
+        }
+    }
+}
+
+// begin: integrate-1 and binning of every particle of resting state q; one
+// thread per cell of layout q.
+template <typename T>
+__global__ __launch_bounds__(256) void k_begin(DevSys<T> D, uint32_t q) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= D.ncells) return;
+    const uint32_t lay = q & 1u;
+    D.count[(q + 2u) % 3u][g] = 0u;
+    const uint32_t n = min(D.count[q % 3u][g], (uint32_t)D.cap);
+    for (uint32_t k = 0; k < n; ++k) {
+        const int64_t slot = g * D.cap + k;
+        const SRec<T> s = D.S[lay][slot];
+        const PRec<T> p = D.P[lay][slot];
+        drift_and_bin<T>(D, q + 1u, s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz, p.tag,
+                         p.type);
+    }
+}
+
+// load: bins host-provided state (tag order) into the layout of state q.
+// vt = v, so a following MODE_INIT pass computes F(x, v; s = q).
+template <typename T>
+__global__ __launch_bounds__(256) void k_load(DevSys<T> D, uint32_t q, const double *x,
+                                              const double *v, const double *f,
+                                              const uint8_t *type) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= D.n) return;
+    double px = wrap_coord(x[3 * i + 0], D.L[0]);
+    double py = wrap_coord(x[3 * i + 1], D.L[1]);
+    double pz = wrap_coord(x[3 * i + 2], D.L[2]);
+    const int cx = cell_coord(px, D.h[0], D.nc[0]);
+    const int cy = cell_coord(py, D.h[1], D.nc[1]);
+    const int cz = cell_coord(pz, D.h[2], D.nc[2]);
+    const int64_t g = cell_linear(cx, cy, cz, D.nc);
+    const uint32_t k = atomicAdd(&D.count[q % 3u][g], 1u);
+    if (k >= (uint32_t)D.cap) {
+        atomicOr(D.err, ERR_CELL_OVERFLOW);
+        return;
+    }
+    const int64_t slot = g * D.cap + k;
+    const uint32_t lay = q & 1u;
+    PRec<T> p;
+    p.ox = (T)(px - (double)cx * D.h[0]);
+    p.oy = (T)(py - (double)cy * D.h[1]);
+    p.oz = (T)(pz - (double)cz * D.h[2]);
+    p.tag = (uint32_t)i;
+    p.vx = (T)v[3 * i + 0];
+    p.vy = (T)v[3 * i + 1];
+    p.vz = (T)v[3 * i + 2];
+    p.type = type ? type[i] : 0u;
+    D.P[lay][slot] = p;
+    SRec<T> s;
+    s.x = px;
+    s.y = py;
+    s.z = pz;
+    s.vx = p.vx;
+    s.vy = p.vy;
+    s.vz = p.vz;
+    s.fx = f ? (T)f[3 * i + 0] : (T)0;
+    s.fy = f ? (T)f[3 * i + 1] : (T)0;
+    s.fz = f ? (T)f[3 * i + 2] : (T)0;
+    D.S[lay][slot] = s;
+    D.slot_of_tag[lay][i] = (uint32_t)slot;
+}
+
+// gather: copies the state of layout q to tag-order FP64 arrays.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(DevSys<T> D, uint32_t q, double *x, double *v,
+                                                double *f, int64_t *cell) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= D.n) return;
+    const uint32_t lay = q & 1u;
+    uint32_t slot = D.slot_of_tag[lay][i];
+    if ((int64_t)slot >= D.ncells * D.cap) {
+        atomicOr(D.err, ERR_INDEX);
+        slot = 0;
+    }
+    const SRec<T> s = D.S[lay][slot];
+    x[3 * i + 0] = s.x;
+    x[3 * i + 1] = s.y;
+    x[3 * i + 2] = s.z;
+    v[3 * i + 0] = (double)s.vx;
+    v[3 * i + 1] = (double)s.vy;
+    v[3 * i + 2] = (double)s.vz;
+    f[3 * i + 0] = (double)s.fx;
+    f[3 * i + 1] = (double)s.fy;
+    f[3 * i + 2] = (double)s.fz;
+    cell[i] = (int64_t)(slot / (uint32_t)D.cap);
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = v;
+}
+
+// Deterministic sums of K per-tag arrays: block b adds tags [b*chunk,
+// (b+1)*chunk) in a fixed tree and writes out[b*K + k].
+template <int K>
+__global__ __launch_bounds__(256) void k_reduce(const double *const *in, int64_t m, int64_t chunk,
+                                                double *out) {
+    __shared__ double s[256];
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = min(lo + chunk, m);
+    for (int k = 0; k < K; ++k) {
+        double acc = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += in[k][i];
+        s[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[(int64_t)blockIdx.x * K + k] = s[0];
+        __syncthreads();
+    }
+}
+
+// Pair counts are integers; u32 -> double per tag before the reduction.
+__global__ __launch_bounds__(256) void k_u32_to_f64(const uint32_t *a, double *b, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) b[i] = (double)a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP>
+static hipError_t launch_force_v(const DevSys<T> &D, uint32_t q, int mode, hipStream_t st) {
+    const int nbx = (D.nc[0] + BX - 1) / BX, nby = (D.nc[1] + BY - 1) / BY,
+              nbz = (D.nc[2] + BZ - 1) / BZ;
+    const int nb = nbx * nby * nbz;
+    switch (mode) {
+    case MODE_INIT:
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_INIT>), dim3(nb), dim3(NT), 0,
+                           st, D, q, nbx, nby, nb);
+        break;
+    case MODE_FINISH:
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FINISH>), dim3(nb), dim3(NT),
+                           0, st, D, q, nbx, nby, nb);
+        break;
+    case MODE_FUSED:
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FUSED>), dim3(nb), dim3(NT), 0,
+                           st, D, q, nbx, nby, nb);
+        break;
+    default:
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_OBS>), dim3(nb), dim3(NT), 0,
+                           st, D, q, nbx, nby, nb);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// Brick variants, selected by index.
+template <typename T>
+hipError_t launch_force(const DevSys<T> &D, uint32_t q, int mode, int variant, hipStream_t st) {
+    switch (variant) {
+    case 0: return launch_force_v<T, 4, 4, 4, 256, 1024>(D, q, mode, st);
+    case 1: return launch_force_v<T, 4, 4, 2, 128, 640>(D, q, mode, st);
+    case 2: return launch_force_v<T, 2, 2, 2, 64, 320>(D, q, mode, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int force_variant_count() { return 3; }
+
+void force_variant_shape(int variant, int out[5]) {
+    static const int t[3][5] = {{4, 4, 4, 256, 1024}, {4, 4, 2, 128, 640}, {2, 2, 2, 64, 320}};
+    for (int k = 0; k < 5; ++k) out[k] = t[variant][k];
+}
+
+template <typename T> hipError_t launch_begin(const DevSys<T> &D, uint32_t q, hipStream_t st) {
+    const int64_t nb = (D.ncells + 255) / 256;
+    hipLaunchKernelGGL(k_begin<T>, dim3((unsigned)nb), dim3(256), 0, st, D, q);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_load(const DevSys<T> &D, uint32_t q, const double *x, const double *v,
+                       const double *f, const uint8_t *type, hipStream_t st) {
+    const int64_t nb = (D.n + 255) / 256;
+    hipLaunchKernelGGL(k_load<T>, dim3((unsigned)nb), dim3(256), 0, st, D, q, x, v, f, type);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather(const DevSys<T> &D, uint32_t q, double *x, double *v, double *f,
+                         int64_t *cell, hipStream_t st) {
+    const int64_t nb = (D.n + 255) / 256;
+    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)nb), dim3(256), 0, st, D, q, x, v, f, cell);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t m, uint32_t v, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, p, m, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_u32_to_f64(const uint32_t *a, double *b, int64_t m, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_u32_to_f64, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, a, b,
+                       m);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce8(const double *const *in, int64_t m, int64_t chunk, int nblocks,
+                          double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce<8>, dim3(nblocks), dim3(256), 0, st, in, m, chunk, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_force<float>(const DevSys<float> &, uint32_t, int, int, hipStream_t);
+template hipError_t launch_force<double>(const DevSys<double> &, uint32_t, int, int, hipStream_t);
+template hipError_t launch_begin<float>(const DevSys<float> &, uint32_t, hipStream_t);
+template hipError_t launch_begin<double>(const DevSys<double> &, uint32_t, hipStream_t);
+template hipError_t launch_load<float>(const DevSys<float> &, uint32_t, const double *,
+                                       const double *, const double *, const uint8_t *,
+                                       hipStream_t);
+template hipError_t launch_load<double>(const DevSys<double> &, uint32_t, const double *,
+                                        const double *, const double *, const uint8_t *,
+                                        hipStream_t);
+template hipError_t launch_gather<float>(const DevSys<float> &, uint32_t, double *, double *,
+                                         double *, int64_t *, hipStream_t);
+template hipError_t launch_gather<double>(const DevSys<double> &, uint32_t, double *, double *,
+                                          double *, int64_t *, hipStream_t);
+
+}  // namespace dpd

@@ -1,0 +1,293 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: binning and pair counts bit-exact; single-evaluation forces max-abs
+<= 1e-4 in mixed precision (FP32 forces, a = 25 scale) and <= 1e-9 in FP64;
+10-step trajectories <= 1e-3 (mixed) and <= 1e-9 (FP64); long-run kT and p
+within 1% of the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1804_06205_amd import dpd
+from paper_1804_06205_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_F = {"mixed": 1e-4, "fp64": 1e-9}
+TOL_X10 = {"mixed": 1e-3, "fp64": 1e-9}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dpd.lib()
+    oracle.lib()
+
+
+def _min_image_diff(a, b, L):
+    d = np.asarray(a) - np.asarray(b)
+    L = np.asarray(L, dtype=float)
+    return d - L * np.rint(d / L)
+
+
+def _gpu_force(w, precision, s=0):
+    """GPU force F(x, v; s) of the workload's state (vt = v)."""
+    with dpd.System.from_workload(w, precision=precision) as g:
+        g.set_state(w.pos, w.vel, None, s)
+        _, _, f, _ = g.get_state()
+    return f
+
+
+def _oracle_force(w, s=0):
+    return oracle.forces(w.pos, w.vel, w.L, w.types, w.params(), w.seed, s, w.bonds())
+
+
+# --------------------------------------------------------------------------
+# Binning and pair counts: bit-exact.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L", [3.0, 5.0, 10.0, 7.5])
+def test_binning_matches_oracle_bit_exact(L):
+    w = W.fluid(L, seed=int(L * 10) + 1)
+    pos = w.pos.copy()
+    rng = np.random.default_rng(5)
+    idx = rng.choice(w.n, size=w.n // 8, replace=False)
+    h = L / np.floor(L)
+    pos[idx, 0] = np.floor(pos[idx, 0] / h) * h            # exactly on cell faces
+    pos[idx[: len(idx) // 2], 1] = np.nextafter(L, 0.0)    # just below L
+    w.pos = pos
+    with dpd.System.from_workload(w) as g:
+        cell, count = g.get_cells()
+    cxyz, ocount, _, _ = oracle.bin_cells(pos, w.L)
+    nx = int(np.floor(L))
+    lin = (cxyz[:, 2] * nx + cxyz[:, 1]) * nx + cxyz[:, 0]
+    np.testing.assert_array_equal(cell, lin)
+    np.testing.assert_array_equal(count, ocount)
+
+
+def test_non_cubic_box_binning():
+    rng = np.random.default_rng(3)
+    L = np.array([3.0, 4.5, 7.25])
+    n = int(3 * L.prod())
+    pos = rng.uniform(0, 1, (n, 3)) * L
+    vel = rng.normal(size=(n, 3))
+    with dpd.System(L, pos, vel) as g:
+        cell, count = g.get_cells()
+    cxyz, ocount, _, _ = oracle.bin_cells(pos, L)
+    nc = np.floor(L).astype(int)
+    np.testing.assert_array_equal(cell, (cxyz[:, 2] * nc[1] + cxyz[:, 1]) * nc[0] + cxyz[:, 0])
+    np.testing.assert_array_equal(count, ocount)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_pair_count_exact_on_quantized_positions(precision):
+    w = W.fluid(10.0, seed=7, quantize=8)
+    with dpd.System.from_workload(w, precision=precision) as g:
+        o = g.observables()
+    ref = oracle.observables(w.pos, w.vel, w.L, w.types, w.a)
+    assert o["npairs"] == ref["npairs"]
+
+
+# --------------------------------------------------------------------------
+# Single force evaluations.
+# --------------------------------------------------------------------------
+
+def _cases():
+    return {
+        "fluid_L10": W.fluid(10.0, seed=1),
+        "fluid_L3": W.fluid(3.0, seed=2),
+        "fluid_L7.5": W.fluid(7.5, seed=3),
+        "melt_L8": W.melt(8.0, seed=4),
+        "peptide_L8": W.peptide(8.0, seed=5, nchains=6, nbeads=20),
+        "helix_L6": W.helix(6.0, seed=6, beads=12),
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_force_parity(name, precision):
+    w = _cases()[name]
+    for s in (0, 17):
+        fg = _gpu_force(w, precision, s)
+        fo = _oracle_force(w, s)
+        err = np.abs(fg - fo).max()
+        assert err <= TOL_F[precision], (name, s, err)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_force_parity_thermalised_state(precision):
+    # A state taken from a trajectory (not a uniform random start).
+    w = W.peptide(8.0, seed=9, nchains=4, nbeads=20)
+    st = oracle.State.from_workload(w).step(30)
+    w.pos, w.vel = st.pos, st.vel
+    err = np.abs(_gpu_force(w, precision, 30) - _oracle_force(w, 30)).max()
+    assert err <= TOL_F[precision]
+
+
+def test_momentum_conservation():
+    w = W.peptide(8.0, seed=12, nchains=6, nbeads=20)
+    f = _gpu_force(w, "mixed", 3)
+    assert np.abs(f.sum(0)).max() <= 1e-5 * np.sqrt(w.n) * np.abs(f).max()
+    f64 = _gpu_force(w, "fp64", 3)
+    assert np.abs(f64.sum(0)).max() <= 1e-10 * np.abs(f64).max()
+
+
+# --------------------------------------------------------------------------
+# Trajectories.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["fluid_L10", "melt_L8", "peptide_L8", "helix_L6"])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_ten_step_trajectory(name, precision):
+    w = _cases()[name]
+    with dpd.System.from_workload(w, precision=precision) as g:
+        g.step(10)
+        xg, vg, fg, step = g.get_state()
+    assert step == 10
+    st = oracle.State.from_workload(w).step(10)
+    dx = np.abs(_min_image_diff(xg, st.pos, w.L)).max()
+    assert dx <= TOL_X10[precision], dx
+
+
+def test_step_splitting_and_determinism_are_bitwise():
+    w = W.peptide(8.0, seed=21, nchains=4, nbeads=20)
+    runs = []
+    for split in ((7,), (3, 4), (1, 1, 5)):
+        with dpd.System.from_workload(w) as g:
+            for k in split:
+                g.step(k)
+            runs.append(g.get_state())
+    for r in runs[1:]:
+        for a, b in zip(r[:3], runs[0][:3]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_checkpoint_resume_is_bitwise():
+    w = W.melt(8.0, seed=22)
+    with dpd.System.from_workload(w) as g:
+        g.step(20)
+        ref = g.get_state()
+    with dpd.System.from_workload(w) as g:
+        g.step(8)
+        x, v, f, s = g.get_state()
+    with dpd.System.from_workload(w) as g2:
+        g2.set_state(x, v, f, s)
+        g2.step(12)
+        got = g2.get_state()
+    for a, b in zip(got[:3], ref[:3]):
+        np.testing.assert_array_equal(a, b)
+    assert got[3] == 20
+
+
+# --------------------------------------------------------------------------
+# Observables.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_observables_match_oracle_on_same_state(precision):
+    w = W.peptide(8.0, seed=31, nchains=6, nbeads=20)
+    with dpd.System.from_workload(w, precision=precision) as g:
+        g.step(5)
+        o = g.observables()
+        x, v, _, _ = g.get_state(force=False)
+    ref = oracle.observables(x, v, w.L, w.types, w.a, w.bonds())
+    rt = 1e-5 if precision == "mixed" else 1e-10
+    for k in ("ke", "u_pair", "u_bond", "w_pair", "w_bond", "pressure", "kT"):
+        assert abs(o[k] - ref[k]) <= rt * max(1.0, abs(ref[k])), (k, o[k], ref[k])
+    np.testing.assert_allclose(o["momentum"], [ref["px"], ref["py"], ref["pz"]], atol=1e-6)
+    assert abs(o["npairs"] - ref["npairs"]) <= (2 if precision == "mixed" else 0)
+
+
+# --------------------------------------------------------------------------
+# Full-size workload (fluid L = 96, 2,654,208 particles).
+# --------------------------------------------------------------------------
+
+def test_full_size_fluid_binning_and_forces():
+    w = W.cfg_fluid_L96()
+    with dpd.System.from_workload(w) as g:
+        cell, count = g.get_cells()
+        g.set_state(w.pos, w.vel, None, 0)
+        _, _, fg, _ = g.get_state()
+    cxyz, ocount, _, _ = oracle.bin_cells(w.pos, w.L)
+    np.testing.assert_array_equal(cell, (cxyz[:, 2] * 96 + cxyz[:, 1]) * 96 + cxyz[:, 0])
+    np.testing.assert_array_equal(count, ocount)
+    fo = _oracle_force(w, 0)
+    err = np.abs(fg - fo).max()
+    assert err <= TOL_F["mixed"], err
+
+
+def test_full_size_pair_count_quantized():
+    w = W.fluid(96.0, seed=3, quantize=8)
+    with dpd.System.from_workload(w) as g:
+        o = g.observables()
+    _, _, _, n_or = oracle.pair_forces(w.pos, w.vel, w.L, w.a, 0.0, 0.0, 1.0, 0, 0)
+    assert o["npairs"] == n_or
+
+
+# --------------------------------------------------------------------------
+# Long-run statistics (fluid L = 10, FP64, as the small benchmark workload).
+# --------------------------------------------------------------------------
+
+def test_long_run_temperature_and_pressure():
+    w = W.cfg_fluid_L10()
+    g = dpd.System.from_workload(w)
+    st = oracle.State.from_workload(w)
+    g.step(200)
+    st.step(200)
+    tg, pg, to, po = [], [], [], []
+    for _ in range(200):
+        g.step(5)
+        st.step(5)
+        og = g.observables()
+        oo = st.observables()
+        tg.append(og["kT"])
+        pg.append(og["pressure"])
+        to.append(oo["kT"])
+        po.append(oo["pressure"])
+    g.close()
+    assert abs(np.mean(tg) - np.mean(to)) <= 0.01 * np.mean(to)
+    assert abs(np.mean(pg) - np.mean(po)) <= 0.01 * np.mean(po)
+
+
+# --------------------------------------------------------------------------
+# Error handling (host-forced; every kernel exits normally).
+# --------------------------------------------------------------------------
+
+def test_cell_capacity_overflow_is_reported():
+    w = W.fluid(5.0, seed=40)
+    pos = w.pos.copy()
+    pos[:20] = [1.5, 1.5, 1.5] + 0.01 * np.arange(20)[:, None]   # 20 in one cell
+    with pytest.raises(dpd.DPDError) as e:
+        dpd.System(w.L, pos, w.vel, cell_capacity=8)
+    assert e.value.code == dpd.ECAPACITY
+
+
+def test_argument_errors():
+    w = W.fluid(5.0, seed=41)
+    with pytest.raises(dpd.DPDError) as e:
+        dpd.System([2.5, 5, 5], w.pos, w.vel)
+    assert e.value.code == dpd.EBOX
+    with dpd.System.from_workload(w) as g:
+        with pytest.raises(dpd.DPDError) as e:
+            g.add_bonds([1], [0], [0], [0.0], [1.0], [0.0])
+        assert e.value.code == dpd.ERANGE
+        with pytest.raises(dpd.DPDError) as e:
+            g.set_params([[25.0]], 4.5, 3.0, 1.0, -0.04)
+        assert e.value.code == dpd.EINVAL
+        g.step(1)
+        with pytest.raises(dpd.DPDError) as e:
+            g.set_params([[25.0]], 4.5, 3.0, 1.0, 0.04)
+        assert e.value.code == dpd.ESTATE
+
+
+def test_nonfinite_state_is_rejected():
+    w = W.fluid(5.0, seed=42)
+    with dpd.System.from_workload(w) as g:
+        v = w.vel.copy()
+        v[3, 1] = np.nan
+        with pytest.raises(dpd.DPDError) as e:
+            g.set_state(w.pos, v)
+        assert e.value.code == dpd.EINVAL
