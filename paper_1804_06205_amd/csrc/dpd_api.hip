@@ -195,9 +195,9 @@ template <typename T> int upload_params(dpd_system *s) {
         for (int64_t b = 0; b < nb; ++b) {
             BondEnt<T> e;
             e.type = s->btype[b];
-            e.r_e = (T)s->bre[b];
-            e.k = (T)s->bk[b];
-            e.alpha = (T)s->balpha[b];
+            e.r_e = s->bre[b];
+            e.k = s->bk[b];
+            e.alpha = s->balpha[b];
             e.partner = (uint32_t)s->bj[b];
             ent[fill[s->bi[b]]++] = e;
             e.partner = (uint32_t)s->bi[b];

@@ -18,11 +18,45 @@ namespace dpd {
 // atomics); kernels restore ascending tag order where summation order matters.
 // ---------------------------------------------------------------------------
 
-// Pair record: what a neighbour needs (position relative to its cell's origin,
-// predicted velocity vt, tag, type).
+// Position of a particle inside its cell, as kept in pair records.
+//  FP32 forces: a fixed-point offset, (x - c h) / h in units of 2^-29.  The
+//    difference of two such offsets (plus a whole-cell shift) is an exact
+//    integer, so a close pair's separation is rounded once, relative to its
+//    own size, when it becomes a float; plain FP32 offsets would carry an
+//    absolute error of ~6e-8 that near-coincident pairs turn into large force
+//    errors.  The same integer difference read from either particle is
+//    exactly negated, so F_ij = -F_ji holds bit for bit.
+//  FP64: the offset x - c h itself.
+template <typename T> struct Geo;
+template <> struct Geo<float> {
+    using P = int32_t;
+    static constexpr double SCALE = 536870912.0;   // 2^29
+    static constexpr int32_t ONE = 1 << 29;
+    __device__ static __forceinline__ P encode(double x, int c, double h) {
+        return (int32_t)rint((x - (double)c * h) / h * SCALE);
+    }
+    // Separation along one axis: a - b - s cells, in length units (hs = h / 2^29).
+    __device__ static __forceinline__ float delta(P a, P b, int s, float hs) {
+        return (float)(a - b - s * ONE) * hs;
+    }
+    __host__ __device__ static float hscale(double h) { return (float)(h / SCALE); }
+};
+template <> struct Geo<double> {
+    using P = double;
+    __device__ static __forceinline__ P encode(double x, int c, double h) {
+        return x - (double)c * h;
+    }
+    __device__ static __forceinline__ double delta(P a, P b, int s, double h) {
+        return (a - b) - (double)s * h;
+    }
+    __host__ __device__ static double hscale(double h) { return h; }
+};
+
+// Pair record: what a neighbour needs (position inside its cell, predicted
+// velocity vt, tag, type).
 template <typename T> struct PRec;
 template <> struct alignas(16) PRec<float> {
-    float ox, oy, oz;
+    int32_t ox, oy, oz;
     uint32_t tag;
     float vx, vy, vz;
     uint32_t type;
@@ -48,11 +82,12 @@ template <> struct alignas(16) SRec<double> {
     double pad;
 };
 
-// One end of a bond record, stored with the particle that owns it.
+// One end of a bond record, stored with the particle that owns it.  Bond
+// terms are evaluated in FP64 in every precision mode.
 template <typename T> struct BondEnt {
     uint32_t partner;   // tag of the other end
     int32_t type;       // 1 harmonic, 2 paper Morse, 3 standard Morse
-    T r_e, k, alpha;
+    double r_e, k, alpha;
 };
 
 // Sticky device error bits.

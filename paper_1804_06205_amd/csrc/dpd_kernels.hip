@@ -32,7 +32,7 @@ constexpr int MAXTYPES = 16;
 enum : int { MODE_INIT = 0, MODE_FINISH = 1, MODE_FUSED = 2, MODE_OBS = 3 };
 
 // Neighbour data staged in LDS.
-template <typename T> struct alignas(16) LA { T ox, oy, oz; uint32_t tag; };
+template <typename T> struct alignas(16) LA { typename Geo<T>::P ox, oy, oz; uint32_t tag; };
 template <typename T> struct alignas(16) LB { T vx, vy, vz; uint32_t type; };
 
 __device__ __forceinline__ int wrapi(int c, int n) {
@@ -133,9 +133,9 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
     const int64_t slot = g * D.cap + k;
     const uint32_t ln = qn & 1u;
     PRec<T> p;
-    p.ox = (T)(x - (double)cx * D.h[0]);
-    p.oy = (T)(y - (double)cy * D.h[1]);
-    p.oz = (T)(z - (double)cz * D.h[2]);
+    p.ox = Geo<T>::encode(x, cx, D.h[0]);
+    p.oy = Geo<T>::encode(y, cy, D.h[1]);
+    p.oz = Geo<T>::encode(z, cz, D.h[2]);
     p.tag = tag;
     p.vx = tx;
     p.vy = ty;
@@ -283,7 +283,9 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
         __syncthreads();
     }
 
-    const T hxT = (T)D.h[0], hyT = (T)D.h[1], hzT = (T)D.h[2];
+    // Per-axis scale from offset units to length.
+    const T hxT = (T)Geo<T>::hscale(D.h[0]), hyT = (T)Geo<T>::hscale(D.h[1]),
+            hzT = (T)Geo<T>::hscale(D.h[2]);
     (void)lane;
     const T gamma = D.gamma, srdt = D.sigma_rdt;
     const int ntypes = D.ntypes;
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
         int oxc = 0, oyc = 0, ozc = 0;
         int64_t slot = 0;
         PRec<T> pi;
-        pi.ox = pi.oy = pi.oz = (T)0;
+        pi.ox = pi.oy = pi.oz = 0;
         pi.vx = pi.vy = pi.vz = (T)0;
         pi.tag = 0xFFFFFFFFu;
         pi.type = 0;
@@ -328,9 +330,9 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                 const int sx = code % 3 - 1, sy = (code / 3) % 3 - 1, sz = code / 9 - 1;
                 const LA<T> a = s_A[j];
                 const LB<T> bj = s_B[j];
-                const T dx = (pi.ox - a.ox) - (T)sx * hxT;
-                const T dy = (pi.oy - a.oy) - (T)sy * hyT;
-                const T dz = (pi.oz - a.oz) - (T)sz * hzT;
+                const T dx = Geo<T>::delta(pi.ox, a.ox, sx, hxT);
+                const T dy = Geo<T>::delta(pi.oy, a.oy, sy, hyT);
+                const T dz = Geo<T>::delta(pi.oz, a.oz, sz, hzT);
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const T aij = arow[bj.type];
                 if (MODE == MODE_OBS) {
@@ -366,7 +368,6 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                 b2 = s_hstart[hr + 2];
                 je = s_hstart[hr + 3];
             }
-            const T syT = (T)dyc * hyT, szT = (T)dzc * hzT;
             const int len = je - jb;
             const int maxlen = wave_max(len);
             const uint32_t rowcode = (uint32_t)(3 * (dyc + 1) + 9 * (dzc + 1));
@@ -375,9 +376,9 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                     const int j = jb + t;
                     const LA<T> a = s_A[j];
                     const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
-                    const T dx = (pi.ox - a.ox) - (T)sx * hxT;
-                    const T dy = (pi.oy - a.oy) - syT;
-                    const T dz = (pi.oz - a.oz) - szT;
+                    const T dx = Geo<T>::delta(pi.ox, a.ox, sx, hxT);
+                    const T dy = Geo<T>::delta(pi.oy, a.oy, dyc, hyT);
+                    const T dz = Geo<T>::delta(pi.oz, a.oz, dzc, hzT);
                     const T r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 < (T)1 && a.tag != pi.tag) {
                         myq[(qt % QCAP) * NT] = (uint32_t)j | ((rowcode + (uint32_t)(sx + 1)) << 16);
@@ -393,9 +394,12 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
 
         if (!have) continue;
 
-        // Bonds (Eq. 8): every record owned by this particle, in input order.
+        // Bonds (Eq. 8): every record owned by this particle, in input order,
+        // evaluated in FP64 (stiff Morse terms reach |F| ~ 1e2, where FP32
+        // rounding alone would exceed the force tolerance).
         const SRec<T> si = D.S[lay][slot];
         double oub = 0.0, owb = 0.0;
+        double gbx = 0.0, gby = 0.0, gbz = 0.0;
         if (D.bond_off) {
             const uint32_t k0 = D.bond_off[pi.tag], k1 = D.bond_off[pi.tag + 1];
             for (uint32_t k = k0; k < k1; ++k) {
@@ -406,18 +410,21 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                     sj = 0;
                 }
                 const SRec<T> &pj = D.S[lay][sj];
-                const T ddx = (T)min_image(si.x - pj.x, D.L[0]);
-                const T ddy = (T)min_image(si.y - pj.y, D.L[1]);
-                const T ddz = (T)min_image(si.z - pj.z, D.L[2]);
-                T u, w;
-                const T c = bond_coef<T>(be.type, ddx * ddx + ddy * ddy + ddz * ddz, be.r_e, be.k,
-                                         be.alpha, u, w);
-                fx += c * ddx;
-                fy += c * ddy;
-                fz += c * ddz;
-                oub += 0.5 * (double)u;
-                owb += 0.5 * (double)w;
+                const double ddx = min_image(si.x - pj.x, D.L[0]);
+                const double ddy = min_image(si.y - pj.y, D.L[1]);
+                const double ddz = min_image(si.z - pj.z, D.L[2]);
+                double u, w;
+                const double c = bond_coef<double>(be.type, ddx * ddx + ddy * ddy + ddz * ddz,
+                                                   be.r_e, be.k, be.alpha, u, w);
+                gbx += c * ddx;
+                gby += c * ddy;
+                gbz += c * ddz;
+                oub += 0.5 * u;
+                owb += 0.5 * w;
             }
+            fx = (T)((double)fx + gbx);
+            fy = (T)((double)fy + gby);
+            fz = (T)((double)fz + gbz);
         }
 
         if (MODE == MODE_OBS) {
@@ -502,9 +509,9 @@ __global__ __launch_bounds__(256) void k_load(DevSys<T> D, uint32_t q, const dou
     const int64_t slot = g * D.cap + k;
     const uint32_t lay = q & 1u;
     PRec<T> p;
-    p.ox = (T)(px - (double)cx * D.h[0]);
-    p.oy = (T)(py - (double)cy * D.h[1]);
-    p.oz = (T)(pz - (double)cz * D.h[2]);
+    p.ox = Geo<T>::encode(px, cx, D.h[0]);
+    p.oy = Geo<T>::encode(py, cy, D.h[1]);
+    p.oz = Geo<T>::encode(pz, cz, D.h[2]);
     p.tag = (uint32_t)i;
     p.vx = (T)v[3 * i + 0];
     p.vy = (T)v[3 * i + 1];

@@ -114,6 +114,7 @@ def test_force_parity(name, precision):
         fg = _gpu_force(w, precision, s)
         fo = _oracle_force(w, s)
         err = np.abs(fg - fo).max()
+        print(f"{name} {precision} s={s}: force max-abs {err:.3e}")
         assert err <= TOL_F[precision], (name, s, err)
 
 
@@ -216,6 +217,7 @@ def test_full_size_fluid_binning_and_forces():
     np.testing.assert_array_equal(count, ocount)
     fo = _oracle_force(w, 0)
     err = np.abs(fg - fo).max()
+    print(f"fluid_L96 force max-abs {err:.3e}")
     assert err <= TOL_F["mixed"], err
 
 
