@@ -182,6 +182,25 @@ int dpd_get_cells(dpd_system *sys, int64_t *cell_of_tag, int64_t *count);
  * out[3] = device bytes held, out[4..6] = cells per axis, out[7] = precision. */
 int dpd_info(dpd_system *sys, int64_t out[8]);
 
+/*
+ * Autotuner.  The pair kernel runs on bricks of BX x BY x BZ cells with a
+ * fixed work-group size and LDS tile; every variant computes bitwise the same
+ * forces, so the choice only changes speed.
+ *   dpd_variant_count()         number of variants.
+ *   dpd_variant_shape(v, out)   out[0..4] = {BX, BY, BZ, threads, LDS capacity}.
+ *   dpd_set_variant(sys, v)     use variant v (-1 = the library's default).
+ *   dpd_autotune(sys, trials, &best, &ms)  times `trials` launches of every
+ *       variant's fused step kernel on the current state, keeps the fastest and
+ *       returns it with its mean time in ms.  The state is left unchanged
+ *       (the trials write only the scratch layout of the next state).
+ *       Synchronises.  Variants whose tile cannot hold the densest brick are
+ *       skipped.
+ */
+int dpd_variant_count(void);
+int dpd_variant_shape(int variant, int out[5]);
+int dpd_set_variant(dpd_system *sys, int variant);
+int dpd_autotune(dpd_system *sys, int trials, int *best_variant, double *best_ms);
+
 /* Frees the system and its device memory (NULL is ignored). */
 void dpd_destroy(dpd_system *sys);
 

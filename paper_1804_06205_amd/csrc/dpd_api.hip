@@ -276,6 +276,10 @@ int load_state(dpd_system *s, const double *pos, const double *vel, const double
     return DPD_OK;
 }
 
+int cells_default_variant(const dpd_system *s) {
+    return s->ncells >= 64 * 1024 ? 0 : (s->ncells >= 8 * 1024 ? 3 : 4);
+}
+
 bool all_finite(const double *p, int64_t m) {
     for (int64_t i = 0; i < m; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -404,8 +408,7 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
         return fail(rc, "%s", msg.c_str());
     }
     // Default brick: the largest one that still gives every CU work.
-    const int64_t cells = s->ncells;
-    s->variant = cells >= 64 * 1024 ? 0 : (cells >= 8 * 1024 ? 1 : 2);
+    s->variant = cells_default_variant(s);
     *out = s;
     return DPD_OK;
 }
@@ -622,6 +625,86 @@ int dpd_observables(dpd_system *s, dpd_obs *out) {
     for (int64_t i = 0; i < n; ++i)
         for (int c = 0; c < 3; ++c) P[c] += p[3 * i + c];
     for (int c = 0; c < 3; ++c) out->momentum[c] = P[c];
+    return DPD_OK;
+}
+
+int dpd_variant_count(void) { return force_variant_count(); }
+
+int dpd_variant_shape(int variant, int out[5]) {
+    if (!out || variant < 0 || variant >= force_variant_count())
+        return fail(DPD_EINVAL, "bad variant %d", variant);
+    force_variant_shape(variant, out);
+    return DPD_OK;
+}
+
+int dpd_set_variant(dpd_system *s, int variant) {
+    if (int rc = check_usable(s)) return rc;
+    if (variant < -1 || variant >= force_variant_count())
+        return fail(DPD_EINVAL, "bad variant %d", variant);
+    s->variant = variant < 0 ? cells_default_variant(s) : variant;
+    return DPD_OK;
+}
+
+int dpd_autotune(dpd_system *s, int trials, int *best_variant, double *best_ms) {
+    if (int rc = check_usable(s)) return rc;
+    if (trials < 1) return fail(DPD_EINVAL, "trials must be >= 1");
+    if (int rc = freeze(s)) return rc;
+    if (int rc = ensure_force(s)) return rc;
+    if (int rc = check_device(s)) return rc;
+    const uint32_t q = (uint32_t)s->t;
+    hipEvent_t ev[2];
+    HIP_OK(hipEventCreate(&ev[0]));
+    HIP_OK(hipEventCreate(&ev[1]));
+    const int keep = s->variant;
+    int best = -1;
+    double best_t = 1e300;
+    for (int v = 0; v < force_variant_count(); ++v) {
+        s->variant = v;
+        double tot = 0.0;
+        bool ok = true;
+        for (int k = 0; k <= trials && ok; ++k) {
+            // The fused pass appends into the next state's counts: clear them.
+            HIP_OK(launch_fill_u32(s->count[(q + 1) % 3], s->ncells, 0u, s->stream));
+            HIP_OK(hipEventRecord(ev[0], s->stream));
+            if (int rc = force(s, q, FORCE_FUSED)) return rc;
+            HIP_OK(hipEventRecord(ev[1], s->stream));
+            HIP_OK(hipEventSynchronize(ev[1]));
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            uint32_t e = 0;
+            HIP_OK(hipMemcpy(&e, s->err, sizeof e, hipMemcpyDeviceToHost));
+            if (e) {
+                // A tile too small for this state: skip the variant, clear the flag
+                // (the trial wrote only scratch memory).
+                ok = false;
+                HIP_OK(hipMemsetAsync(s->err, 0, sizeof(uint32_t), s->stream));
+                if (e & ~(uint32_t)ERR_TILE_OVERFLOW) {
+                    s->variant = keep;
+                    (void)hipEventDestroy(ev[0]);
+                    (void)hipEventDestroy(ev[1]);
+                    HIP_OK(hipStreamSynchronize(s->stream));
+                    HIP_OK(hipMemcpy(s->err, &e, sizeof e, hipMemcpyHostToDevice));
+                    return check_device(s);
+                }
+            }
+            if (k > 0) tot += ms;
+        }
+        if (ok && tot / trials < best_t) {
+            best_t = tot / trials;
+            best = v;
+        }
+    }
+    HIP_OK(launch_fill_u32(s->count[(q + 1) % 3], s->ncells, 0u, s->stream));
+    HIP_OK(hipStreamSynchronize(s->stream));
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (best < 0) {
+        s->variant = keep;
+        return fail(DPD_ECAPACITY, "no brick variant can hold this state's densest neighbourhood");
+    }
+    s->variant = best;
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t;
     return DPD_OK;
 }
 

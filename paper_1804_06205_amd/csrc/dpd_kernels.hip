@@ -21,12 +21,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+#include <type_traits>
+
 #include "dpd_device.hpp"
 #include "dpd_kernels.hpp"
 
 namespace dpd {
 
-constexpr int QCAP = 8;          // per-lane pending-pair queue depth
+constexpr int QCAP = 8;          // per-lane pending-pair queue depth (>= 5)
 constexpr int MAXTYPES = 16;
 
 enum : int { MODE_INIT = 0, MODE_FINISH = 1, MODE_FUSED = 2, MODE_OBS = 3 };
@@ -158,30 +161,110 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
 
 // ---------------------------------------------------------------------------
 // Pair + bond force over one brick of BX x BY x BZ cells.
+//
+// The work-group stages the brick's neighbourhood (its cells plus one layer,
+// periodic) in LDS with ascending tag order inside every cell.  Each lane owns
+// one particle i and walks the 9 rows of 3 consecutive halo cells that hold
+// its 27 neighbour cells, in a fixed order, so i adds its pair forces in the
+// same order on every run.  In-range neighbours are queued per lane in LDS and
+// the expensive pair term (Philox, Box-Muller, force) runs once three quarters
+// of the lanes hold a queued neighbour, which keeps the 64-wide wave busy
+// although only ~15% of the candidates are within the cutoff.
+//
+// IGEO (mixed precision, cubic cells): LDS holds brick-frame fixed-point
+// coordinates (cell offset + halo cell index, in units of 2^-29 cells, as
+// u32), so a candidate's squared distance is an exact 64-bit integer and the
+// cutoff test is three subtractions and three 32x32->64 multiply-adds.
+// Otherwise (FP64, or non-cubic cells) LDS holds cell-local offsets and the
+// whole-cell shift of each neighbour is applied explicitly.
 // ---------------------------------------------------------------------------
-template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE>
+struct alignas(16) LAI { uint32_t qx, qy, qz, tag; };
+
+// Copies halo cells [c0, c1) into LDS at their offsets relative to cell c0,
+// one thread per cell, then sorts every cell's records by tag in place.
+template <typename T, int HX, int HY, int NHC, int NT, bool IGEO, typename AT>
+__device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, const int *s_hcell,
+                                            const int *s_hstart, int c0, int c1, AT *s_A,
+                                            LB<T> *s_B) {
+    const int cap = D.cap;
+    const int off0 = s_hstart[c0];
+    for (int hc = c0 + (int)threadIdx.x; hc < c1; hc += NT) {
+        const int lo = s_hstart[hc] - off0, n = s_hstart[hc + 1] - s_hstart[hc];
+        if (n == 0) continue;
+        const PRec<T> *src = D.P[lay] + (int64_t)s_hcell[hc] * cap;
+        const uint32_t hx = (uint32_t)(hc % HX), hy = (uint32_t)((hc / HX) % HY),
+                       hz = (uint32_t)(hc / (HX * HY));
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            PRec<T> r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k0 + u < n) r[u] = src[k0 + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k0 + u < n) {
+                    AT a;
+                    if constexpr (IGEO) {
+                        a.qx = (uint32_t)r[u].ox + (hx << 29);
+                        a.qy = (uint32_t)r[u].oy + (hy << 29);
+                        a.qz = (uint32_t)r[u].oz + (hz << 29);
+                    } else {
+                        a.ox = r[u].ox;
+                        a.oy = r[u].oy;
+                        a.oz = r[u].oz;
+                    }
+                    a.tag = r[u].tag;
+                    LB<T> bb;
+                    bb.vx = r[u].vx;
+                    bb.vy = r[u].vy;
+                    bb.vz = r[u].vz;
+                    bb.type = r[u].type;
+                    s_A[lo + k0 + u] = a;
+                    s_B[lo + k0 + u] = bb;
+                }
+            }
+        }
+        for (int i = lo + 1; i < lo + n; ++i) {
+            const AT a = s_A[i];
+            const LB<T> bb = s_B[i];
+            int j = i - 1;
+            while (j >= lo && s_A[j].tag > a.tag) {
+                s_A[j + 1] = s_A[j];
+                s_B[j + 1] = s_B[j];
+                --j;
+            }
+            s_A[j + 1] = a;
+            s_B[j + 1] = bb;
+        }
+    }
+}
+
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO>
 __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, int nby,
-                                              int nbricks) {
+                                              int nbricks, uint64_t thr) {
     constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
     constexpr int NHC = HX * HY * HZ;
     constexpr int NOC = BX * BY * BZ;
-    constexpr int RPT = (HCAP + NT - 1) / NT;
     constexpr int IPT_H = (NHC + 1 + NT - 1) / NT;
     constexpr int IPT_O = (NOC + 1 + NT - 1) / NT;
-    static_assert(QCAP * NT >= HCAP, "queue area doubles as the tag scratch");
+    // Brick-frame fixed point: 2^29 units per cell (the pair records' own
+    // scale, so every brick shape gives bitwise the same forces); the largest
+    // coordinate, (halo extent) * 2^29, must fit in 32 bits.
+    constexpr int HMAX = HX > HY ? (HX > HZ ? HX : HZ) : (HY > HZ ? HY : HZ);
+    static_assert(!IGEO || HMAX <= 7, "brick too large for the u32 brick frame");
+    using AT = typename std::conditional<IGEO, LAI, LA<T>>::type;
 
     __shared__ int s_hcell[NHC];
     __shared__ int s_hstart[NHC + 1];
     __shared__ int s_ostart[NOC + 1];
+    __shared__ int s_chunk[NHC + 1];
     __shared__ int s_wave[NT / 64];
-    __shared__ int s_flag;
+    __shared__ int s_flag, s_nchunk;
     __shared__ T s_a[MAXTYPES * MAXTYPES];
-    __shared__ LA<T> s_A[HCAP];
+    __shared__ AT s_A[HCAP + 1];     // + one far-away sentinel (IGEO)
     __shared__ LB<T> s_B[HCAP];
     __shared__ uint32_t s_q[QCAP * NT];
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
     const uint32_t lay = q & 1u;
     const uint32_t *cnt = D.count[q % 3u];
     const int cap = D.cap;
@@ -223,6 +306,15 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                 cz2[cell_linear(c0x + ox, c0y + oy, c0z + oz, D.nc)] = 0u;
         }
     }
+    if constexpr (IGEO) {
+        if (tid == 0) {
+            // At least one cell away from every own particle in each axis.
+            LAI sent;
+            sent.qx = sent.qy = sent.qz = 0u;
+            sent.tag = 0xFFFFFFFFu;
+            s_A[HCAP] = sent;
+        }
+    }
     __syncthreads();
     block_scan<NT, IPT_H>(s_hstart, NHC, s_wave);
     for (int oc = tid; oc < NOC; oc += NT) {
@@ -234,62 +326,41 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
         }
         s_ostart[oc] = c;
     }
+    // Chunks of whole halo cells that fit the LDS tile, in cell order (one
+    // chunk unless the neighbourhood is unusually dense).
+    if (tid == 0) {
+        int k = 0;
+        s_chunk[0] = 0;
+        if (s_hstart[NHC] > HCAP) {
+            int base = 0;
+            for (int hc = 0; hc < NHC; ++hc)
+                if (s_hstart[hc + 1] - base > HCAP) {
+                    s_chunk[++k] = hc;
+                    base = s_hstart[hc];
+                }
+        }
+        s_chunk[++k] = NHC;
+        s_nchunk = k;
+    }
     __syncthreads();
     block_scan<NT, IPT_O>(s_ostart, NOC, s_wave);
-    const int ntot = s_hstart[NHC];
     const int nown = s_ostart[NOC];
-    if (ntot > HCAP) {
-        if (tid == 0) atomicOr(D.err, ERR_TILE_OVERFLOW);
-        return;
-    }
-
-    // Stage the neighbourhood in LDS, ascending tag order inside each cell.
-    {
-        PRec<T> rec[RPT];
-        int hcs[RPT];
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int u = tid + r * NT;
-            hcs[r] = -1;
-            if (u < ntot) {
-                const int hc = find_bin(s_hstart, NHC, u);
-                hcs[r] = hc;
-                rec[r] = D.P[lay][(int64_t)s_hcell[hc] * cap + (u - s_hstart[hc])];
-                s_q[u] = rec[r].tag;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            if (hcs[r] >= 0) {
-                const int lo = s_hstart[hcs[r]], hi = s_hstart[hcs[r] + 1];
-                int rank = 0;
-                for (int v = lo; v < hi; ++v) rank += s_q[v] < rec[r].tag ? 1 : 0;
-                const int d = lo + rank;
-                LA<T> a;
-                a.ox = rec[r].ox;
-                a.oy = rec[r].oy;
-                a.oz = rec[r].oz;
-                a.tag = rec[r].tag;
-                LB<T> bb;
-                bb.vx = rec[r].vx;
-                bb.vy = rec[r].vy;
-                bb.vz = rec[r].vz;
-                bb.type = rec[r].type;
-                s_A[d] = a;
-                s_B[d] = bb;
-            }
-        }
+    const int nchunk = s_nchunk;
+    if (nchunk == 1) {
+        stage_cells<T, HX, HY, NHC, NT, IGEO, AT>(D, lay, s_hcell, s_hstart, 0, NHC, s_A, s_B);
         __syncthreads();
     }
 
     // Per-axis scale from offset units to length.
     const T hxT = (T)Geo<T>::hscale(D.h[0]), hyT = (T)Geo<T>::hscale(D.h[1]),
             hzT = (T)Geo<T>::hscale(D.h[2]);
-    (void)lane;
     const T gamma = D.gamma, srdt = D.sigma_rdt;
     const int ntypes = D.ntypes;
     uint32_t *myq = s_q + tid;
+    // In-range test as one unsigned compare: r2 - 1 < thr - 1 also rejects
+    // r2 = 0, i.e. i itself (in the observables pass, which counts coincident
+    // pairs too, i is excluded by tag instead).
+    const uint64_t thr1 = thr - 1u;
 
     for (int base = 0; base < nown; base += NT) {
         const int qi = base + tid;
@@ -310,15 +381,22 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
             slot = (int64_t)s_hcell[hc] * cap + (qi - s_ostart[oc]);
             pi = D.P[lay][slot];
         }
+        // Brick-frame coordinates of i (IGEO).
+        uint32_t pqx = 0, pqy = 0, pqz = 0;
+        if constexpr (IGEO) {
+            pqx = (uint32_t)pi.ox + ((uint32_t)(oxc + 1) << 29);
+            pqy = (uint32_t)pi.oy + ((uint32_t)(oyc + 1) << 29);
+            pqz = (uint32_t)pi.oz + ((uint32_t)(ozc + 1) << 29);
+        }
         const T *arow = s_a + (int)pi.type * ntypes;
-        // Lanes with a particle; pending pairs are processed once 3/4 of them
-        // have one queued.
-        const int nact = __popcll(__ballot(have));
-        const int rth = max(1, (3 * nact) / 4);
         T fx = 0, fy = 0, fz = 0;
         double ou = 0.0, ow = 0.0;
         uint32_t onp = 0;
         uint32_t qh = 0, qt = 0;
+        // Lanes with a particle; pending pairs are processed once 3/4 of them
+        // have one queued.
+        const int nact = __popcll(__ballot(have));
+        const int rth = max(1, (3 * nact) / 4);
 
         // Pops one queued neighbour per lane that has one and adds its force.
         auto process = [&]() {
@@ -326,13 +404,21 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                 const uint32_t e = myq[(qh % QCAP) * NT];
                 ++qh;
                 const int j = (int)(e & 0xFFFFu);
-                const int code = (int)(e >> 16);
-                const int sx = code % 3 - 1, sy = (code / 3) % 3 - 1, sz = code / 9 - 1;
-                const LA<T> a = s_A[j];
+                const AT a = s_A[j];
                 const LB<T> bj = s_B[j];
-                const T dx = Geo<T>::delta(pi.ox, a.ox, sx, hxT);
-                const T dy = Geo<T>::delta(pi.oy, a.oy, sy, hyT);
-                const T dz = Geo<T>::delta(pi.oz, a.oz, sz, hzT);
+                T dx, dy, dz;
+                if constexpr (IGEO) {
+                    dx = (T)(int32_t)(pqx - a.qx) * hxT;
+                    dy = (T)(int32_t)(pqy - a.qy) * hyT;
+                    dz = (T)(int32_t)(pqz - a.qz) * hzT;
+                } else {
+                    const int code = (int)(e >> 16);
+                    const int sx = (code & 3) - 1, sy = ((code >> 2) & 3) - 1,
+                              sz = ((code >> 4) & 3) - 1;
+                    dx = Geo<T>::delta(pi.ox, a.ox, sx, hxT);
+                    dy = Geo<T>::delta(pi.oy, a.oy, sy, hyT);
+                    dz = Geo<T>::delta(pi.oz, a.oz, sz, hzT);
+                }
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const T aij = arow[bj.type];
                 if (MODE == MODE_OBS) {
@@ -344,8 +430,8 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                         ow += (double)(aij * w * r);
                     }
                 } else if (r2 > (T)0) {
-                    const T r = t_sqrt(r2);
-                    const T rinv = (T)1 / r;
+                    const T rinv = t_rsqrt(r2);
+                    const T r = r2 * rinv;
                     const T w = (T)1 - r;
                     const T edv = (dx * (pi.vx - bj.vx) + dy * (pi.vy - bj.vy) +
                                    dz * (pi.vz - bj.vz)) * rinv;
@@ -358,39 +444,85 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
             }
         };
 
-        for (int row = 0; row < 9; ++row) {
-            const int dyc = row % 3 - 1, dzc = row / 3 - 1;
-            int jb = 0, b1 = 0, b2 = 0, je = 0;
-            if (have) {
-                const int hr = ((ozc + 1 + dzc) * HY + (oyc + 1 + dyc)) * HX + oxc;
-                jb = s_hstart[hr];
-                b1 = s_hstart[hr + 1];
-                b2 = s_hstart[hr + 2];
-                je = s_hstart[hr + 3];
+        for (int k = 0; k < nchunk; ++k) {
+            const int clo = s_chunk[k], chi = s_chunk[k + 1];
+            const int off0 = s_hstart[clo];
+            if (nchunk > 1) {
+                __syncthreads();
+                stage_cells<T, HX, HY, NHC, NT, IGEO, AT>(D, lay, s_hcell, s_hstart, clo, chi,
+                                                         s_A, s_B);
+                __syncthreads();
             }
-            const int len = je - jb;
-            const int maxlen = wave_max(len);
-            const uint32_t rowcode = (uint32_t)(3 * (dyc + 1) + 9 * (dzc + 1));
-            for (int t = 0; t < maxlen; ++t) {
-                if (t < len) {
-                    const int j = jb + t;
-                    const LA<T> a = s_A[j];
-                    const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
-                    const T dx = Geo<T>::delta(pi.ox, a.ox, sx, hxT);
-                    const T dy = Geo<T>::delta(pi.oy, a.oy, dyc, hyT);
-                    const T dz = Geo<T>::delta(pi.oz, a.oz, dzc, hzT);
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < (T)1 && a.tag != pi.tag) {
-                        myq[(qt % QCAP) * NT] = (uint32_t)j | ((rowcode + (uint32_t)(sx + 1)) << 16);
-                        ++qt;
+            // Candidate scan: rows of three consecutive halo cells (clipped to
+            // the chunk), four candidates per step with the LDS reads issued up
+            // front; misses are written to the free queue slot and not counted,
+            // so the step has no branches.  Before each step every queue has
+            // room for four more.
+            for (int row = 0; row < 9; ++row) {
+                const int dyc = row % 3 - 1, dzc = row / 3 - 1;
+                int jb = 0, b1 = 0, b2 = 0, je = 0;
+                if (have) {
+                    const int hr = ((ozc + 1 + dzc) * HY + (oyc + 1 + dyc)) * HX + oxc;
+                    const int r0 = max(hr, clo), r1 = min(hr + 3, chi);
+                    if (r0 < r1) {
+                        jb = s_hstart[r0] - off0;
+                        je = s_hstart[r1] - off0;
+                    }
+                    if constexpr (!IGEO) {
+                        b1 = s_hstart[hr + 1] - off0;
+                        b2 = s_hstart[hr + 2] - off0;
                     }
                 }
-                const uint64_t pend = __ballot(qt != qh);
-                const uint64_t full = __ballot(qt - qh == (uint32_t)QCAP);
-                if (__popcll(pend) >= rth || full) process();
+                const int len = je - jb;
+                const uint32_t rowcode = (uint32_t)(((dyc + 1) << 2) | ((dzc + 1) << 4));
+                for (int t = 0; __ballot(t < len); t += 4) {
+                    AT a[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        int jj;
+                        if constexpr (IGEO) jj = t + u < len ? jb + t + u : HCAP;
+                        else jj = min(jb + t + u, max(je - 1, 0));
+                        a[u] = s_A[jj];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = jb + t + u;
+                        bool hit;
+                        uint32_t code = 0;
+                        if constexpr (IGEO) {
+                            const int32_t ddx = (int32_t)(pqx - a[u].qx);
+                            const int32_t ddy = (int32_t)(pqy - a[u].qy);
+                            const int32_t ddz = (int32_t)(pqz - a[u].qz);
+                            if (MODE == MODE_OBS) {
+                                const uint64_t r2 = (uint64_t)((int64_t)ddx * ddx +
+                                                               (int64_t)ddy * ddy +
+                                                               (int64_t)ddz * ddz);
+                                hit = (r2 < thr) & (a[u].tag != pi.tag);
+                            } else {
+                                const uint64_t r2m1 = (uint64_t)((int64_t)ddx * ddx - 1 +
+                                                                 (int64_t)ddy * ddy +
+                                                                 (int64_t)ddz * ddz);
+                                hit = r2m1 < thr1;
+                            }
+                        } else {
+                            const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
+                            const T dx = Geo<T>::delta(pi.ox, a[u].ox, sx, hxT);
+                            const T dy = Geo<T>::delta(pi.oy, a[u].oy, dyc, hyT);
+                            const T dz = Geo<T>::delta(pi.oz, a[u].oz, dzc, hzT);
+                            hit = (dx * dx + dy * dy + dz * dz < (T)1) & (t + u < len) &
+                                  (a[u].tag != pi.tag);
+                            code = rowcode | (uint32_t)(sx + 1);
+                        }
+                        myq[(qt % QCAP) * NT] = (uint32_t)j | (code << 16);
+                        qt += hit ? 1u : 0u;
+                    }
+                    if (__popcll(__ballot(qt != qh)) >= rth) process();
+                    while (__ballot(qt - qh > (uint32_t)(QCAP - 4))) process();
+                }
             }
+            // Queue entries index this chunk's LDS contents: drain before the next.
+            while (__ballot(qt != qh)) process();
         }
-        while (__ballot(qt != qh)) process();
 
         if (!have) continue;
 
@@ -594,47 +726,72 @@ __global__ __launch_bounds__(256) void k_u32_to_f64(const uint32_t *a, double *b
 // Host launchers.
 // ---------------------------------------------------------------------------
 
-template <typename T, int BX, int BY, int BZ, int NT, int HCAP>
-static hipError_t launch_force_v(const DevSys<T> &D, uint32_t q, int mode, hipStream_t st) {
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP, bool IGEO>
+static hipError_t launch_force_g(const DevSys<T> &D, uint32_t q, int mode, hipStream_t st) {
     const int nbx = (D.nc[0] + BX - 1) / BX, nby = (D.nc[1] + BY - 1) / BY,
               nbz = (D.nc[2] + BZ - 1) / BZ;
     const int nb = nbx * nby * nbz;
+    // Cutoff r^2 < 1 in squared fixed-point units: sum dq^2 < (2^29 / h)^2.
+    const double lim = 536870912.0 / D.h[0];
+    const uint64_t thr = (uint64_t)std::ceil(lim * lim);
     switch (mode) {
     case MODE_INIT:
-        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_INIT>), dim3(nb), dim3(NT), 0,
-                           st, D, q, nbx, nby, nb);
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_INIT, IGEO>), dim3(nb), dim3(NT),
+                           0, st, D, q, nbx, nby, nb, thr);
         break;
     case MODE_FINISH:
-        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FINISH>), dim3(nb), dim3(NT),
-                           0, st, D, q, nbx, nby, nb);
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FINISH, IGEO>), dim3(nb),
+                           dim3(NT), 0, st, D, q, nbx, nby, nb, thr);
         break;
     case MODE_FUSED:
-        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FUSED>), dim3(nb), dim3(NT), 0,
-                           st, D, q, nbx, nby, nb);
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FUSED, IGEO>), dim3(nb),
+                           dim3(NT), 0, st, D, q, nbx, nby, nb, thr);
         break;
     default:
-        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_OBS>), dim3(nb), dim3(NT), 0,
-                           st, D, q, nbx, nby, nb);
+        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_OBS, IGEO>), dim3(nb), dim3(NT),
+                           0, st, D, q, nbx, nby, nb, thr);
         break;
     }
     return hipGetLastError();
 }
 
-// Brick variants, selected by index.
+// Mixed precision with cubic cells uses the integer brick frame.
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP>
+static hipError_t launch_force_v(const DevSys<T> &D, uint32_t q, int mode, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (D.h[0] == D.h[1] && D.h[0] == D.h[2])
+            return launch_force_g<T, BX, BY, BZ, NT, HCAP, true>(D, q, mode, st);
+    }
+    return launch_force_g<T, BX, BY, BZ, NT, HCAP, false>(D, q, mode, st);
+}
+
+// Brick variants, selected by index: {BX, BY, BZ, threads, LDS capacity}.
+#define DPD_VARIANTS(X)                                                                   \
+    X(0, 4, 4, 4, 256, 1024)                                                              \
+    X(1, 5, 4, 4, 256, 1152)                                                              \
+    X(2, 5, 5, 4, 320, 1344)                                                              \
+    X(3, 4, 4, 2, 128, 640)                                                               \
+    X(4, 2, 2, 2, 64, 320)
+
 template <typename T>
 hipError_t launch_force(const DevSys<T> &D, uint32_t q, int mode, int variant, hipStream_t st) {
     switch (variant) {
-    case 0: return launch_force_v<T, 4, 4, 4, 256, 1024>(D, q, mode, st);
-    case 1: return launch_force_v<T, 4, 4, 2, 128, 640>(D, q, mode, st);
-    case 2: return launch_force_v<T, 2, 2, 2, 64, 320>(D, q, mode, st);
+#define DPD_CASE(i, bx, by, bz, nt, hc)                                                   \
+    case i: return launch_force_v<T, bx, by, bz, nt, hc>(D, q, mode, st);
+        DPD_VARIANTS(DPD_CASE)
+#undef DPD_CASE
     default: return hipErrorInvalidValue;
     }
 }
 
-int force_variant_count() { return 3; }
+int force_variant_count() { return 5; }
 
 void force_variant_shape(int variant, int out[5]) {
-    static const int t[3][5] = {{4, 4, 4, 256, 1024}, {4, 4, 2, 128, 640}, {2, 2, 2, 64, 320}};
+    static const int t[5][5] = {
+#define DPD_ROW(i, bx, by, bz, nt, hc) {bx, by, bz, nt, hc},
+        DPD_VARIANTS(DPD_ROW)
+#undef DPD_ROW
+    };
     for (int k = 0; k < 5; ++k) out[k] = t[variant][k];
 }
 

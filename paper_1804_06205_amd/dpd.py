@@ -70,6 +70,11 @@ SIGNATURES = {
     "dpd_get_cells": (ctypes.c_int, [_vp, _i64, _i64]),
     "dpd_info": (ctypes.c_int, [_vp, _i64]),
     "dpd_destroy": (None, [_vp]),
+    "dpd_variant_count": (ctypes.c_int, []),
+    "dpd_variant_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "dpd_set_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dpd_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -89,6 +94,16 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def variants() -> list:
+    """Shapes {BX, BY, BZ, threads, LDS capacity} of the pair-kernel variants."""
+    out = []
+    for v in range(lib().dpd_variant_count()):
+        a = (ctypes.c_int * 5)()
+        _check(lib().dpd_variant_shape(v, a))
+        out.append(tuple(a))
+    return out
 
 
 def last_error() -> str:
@@ -219,6 +234,16 @@ class System:
         count = np.zeros(info["ncells"], np.int64)
         _check(lib().dpd_get_cells(self._h, _p(cell, _i64), _p(count, _i64)))
         return cell, count
+
+    def set_variant(self, variant: int):
+        _check(lib().dpd_set_variant(self._h, variant))
+
+    def autotune(self, trials: int = 3):
+        """Times every brick variant on the current state; keeps the fastest."""
+        v = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(lib().dpd_autotune(self._h, trials, ctypes.byref(v), ctypes.byref(ms)))
+        return v.value, ms.value
 
     def info(self) -> dict:
         out = np.zeros(8, np.int64)

@@ -293,3 +293,61 @@ def test_nonfinite_state_is_rejected():
         with pytest.raises(dpd.DPDError) as e:
             g.set_state(w.pos, v)
         assert e.value.code == dpd.EINVAL
+
+
+# --------------------------------------------------------------------------
+# Brick variants, chunked neighbourhoods and the autotuner.
+# --------------------------------------------------------------------------
+
+def test_dense_box_uses_chunked_neighbourhoods():
+    # rho = 6: a 2x2x2 brick's 64-cell neighbourhood holds ~384 particles,
+    # more than its 320-slot tile, so the kernel processes it in chunks.
+    w = W.fluid(6.0, rho=6.0, seed=50)
+    with dpd.System.from_workload(w) as g:
+        g.set_variant(4)
+        g.set_state(w.pos, w.vel, None, 2)
+        _, _, f, _ = g.get_state()
+        g.step(3)
+        x, _, _, _ = g.get_state()
+    fo = _oracle_force(w, 2)
+    assert np.abs(f - fo).max() <= TOL_F["mixed"]
+    st = oracle.State(w.pos, w.vel, w.L, w.types, w.params(), w.seed, step=2).step(3)
+    assert np.abs(_min_image_diff(x, st.pos, w.L)).max() <= TOL_X10["mixed"]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_every_brick_variant_gives_bitwise_identical_steps(precision):
+    w = W.peptide(10.0, seed=51, nchains=5, nbeads=20)
+    ref = None
+    for v in range(len(dpd.variants())):
+        with dpd.System.from_workload(w, precision=precision) as g:
+            g.set_variant(v)
+            g.step(6)
+            got = g.get_state()
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(got[:3], ref[:3]):
+                np.testing.assert_array_equal(a, b)
+
+
+def test_autotune_leaves_the_state_unchanged():
+    w = W.melt(12.0, seed=52)
+    with dpd.System.from_workload(w) as g:
+        g.step(4)
+        before = g.get_state()
+        v, ms = g.autotune(2)
+        assert 0 <= v < len(dpd.variants()) and ms > 0
+        after = g.get_state()
+        for a, b in zip(after[:3], before[:3]):
+            np.testing.assert_array_equal(a, b)
+    with dpd.System.from_workload(w) as g2:
+        g2.step(7)
+        ref = g2.get_state()
+    with dpd.System.from_workload(w) as g3:
+        g3.step(4)
+        g3.autotune(2)
+        g3.step(3)
+        got = g3.get_state()
+    for a, b in zip(got[:3], ref[:3]):
+        np.testing.assert_array_equal(a, b)
