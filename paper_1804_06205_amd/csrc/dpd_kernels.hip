@@ -110,7 +110,8 @@ __device__ __forceinline__ int xcd_brick(int bid, int nb) {
 template <typename T>
 __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, double x,
                                               double y, double z, T vx, T vy, T vz, T fx,
-                                              T fy, T fz, uint32_t tag, uint32_t type) {
+                                              T fy, T fz, uint32_t tag, uint32_t type,
+                                              bool bonded) {
     const double dx = D.dt_d * (double)vx + D.half_dt2_d * (double)fx;
     const double dy = D.dt_d * (double)vy + D.half_dt2_d * (double)fy;
     const double dz = D.dt_d * (double)vz + D.half_dt2_d * (double)fz;
@@ -156,7 +157,10 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
     s.fy = fy;
     s.fz = fz;
     D.S[ln][slot] = s;
-    D.slot_of_tag[ln][tag] = (uint32_t)slot;
+    // The tag -> slot map is read only to find bond partners; keep it for
+    // bonded particles (a scattered 4-byte store costs a whole memory burst)
+    // and rebuild it in full before any read-back.
+    if (bonded) D.slot_of_tag[ln][tag] = (uint32_t)slot;
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +266,10 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
     __shared__ T s_a[MAXTYPES * MAXTYPES];
     __shared__ AT s_A[HCAP + 1];     // + one far-away sentinel (IGEO)
     __shared__ LB<T> s_B[HCAP];
-    __shared__ uint32_t s_q[QCAP * NT];
+    // Per-lane queues of pending neighbours: LDS indices (u16) in the integer
+    // frame; index plus whole-cell shift code (u32) otherwise.
+    using QT = typename std::conditional<IGEO, uint16_t, uint32_t>::type;
+    __shared__ QT s_q[QCAP * NT];
 
     const int tid = threadIdx.x;
     const uint32_t lay = q & 1u;
@@ -346,17 +353,13 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
     block_scan<NT, IPT_O>(s_ostart, NOC, s_wave);
     const int nown = s_ostart[NOC];
     const int nchunk = s_nchunk;
-    if (nchunk == 1) {
-        stage_cells<T, HX, HY, NHC, NT, IGEO, AT>(D, lay, s_hcell, s_hstart, 0, NHC, s_A, s_B);
-        __syncthreads();
-    }
 
     // Per-axis scale from offset units to length.
     const T hxT = (T)Geo<T>::hscale(D.h[0]), hyT = (T)Geo<T>::hscale(D.h[1]),
             hzT = (T)Geo<T>::hscale(D.h[2]);
     const T gamma = D.gamma, srdt = D.sigma_rdt;
     const int ntypes = D.ntypes;
-    uint32_t *myq = s_q + tid;
+    QT *myq = s_q + tid;
     // In-range test as one unsigned compare: r2 - 1 < thr - 1 also rejects
     // r2 = 0, i.e. i itself (in the observables pass, which counts coincident
     // pairs too, i is excluded by tag instead).
@@ -381,6 +384,13 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
             slot = (int64_t)s_hcell[hc] * cap + (qi - s_ostart[oc]);
             pi = D.P[lay][slot];
         }
+        if (base == 0 && nchunk == 1) {
+            // Stage the whole neighbourhood once; the own-particle load above
+            // is already in flight.
+            stage_cells<T, HX, HY, NHC, NT, IGEO, AT>(D, lay, s_hcell, s_hstart, 0, NHC, s_A,
+                                                     s_B);
+            __syncthreads();
+        }
         // Brick-frame coordinates of i (IGEO).
         uint32_t pqx = 0, pqy = 0, pqz = 0;
         if constexpr (IGEO) {
@@ -399,9 +409,9 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
         const int rth = max(1, (3 * nact) / 4);
 
         // Pops one queued neighbour per lane that has one and adds its force.
-        auto process = [&]() {
+        auto process = [&]() __attribute__((always_inline)) {
             if (qt != qh) {
-                const uint32_t e = myq[(qh % QCAP) * NT];
+                const uint32_t e = (uint32_t)myq[(qh % QCAP) * NT];
                 ++qh;
                 const int j = (int)(e & 0xFFFFu);
                 const AT a = s_A[j];
@@ -513,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                                   (a[u].tag != pi.tag);
                             code = rowcode | (uint32_t)(sx + 1);
                         }
-                        myq[(qt % QCAP) * NT] = (uint32_t)j | (code << 16);
+                        myq[(qt % QCAP) * NT] = (QT)((uint32_t)j | (code << 16));
                         qt += hit ? 1u : 0u;
                     }
                     if (__popcll(__ballot(qt != qh)) >= rth) process();
@@ -532,8 +542,10 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
         const SRec<T> si = D.S[lay][slot];
         double oub = 0.0, owb = 0.0;
         double gbx = 0.0, gby = 0.0, gbz = 0.0;
+        uint32_t nbond = 0;
         if (D.bond_off) {
             const uint32_t k0 = D.bond_off[pi.tag], k1 = D.bond_off[pi.tag + 1];
+            nbond = k1 - k0;
             for (uint32_t k = k0; k < k1; ++k) {
                 const BondEnt<T> be = D.bonds[k];
                 uint32_t sj = D.slot_of_tag[lay][be.partner];
@@ -595,7 +607,8 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
             sp->fy = fy;
             sp->fz = fz;
         } else {
-            drift_and_bin<T>(D, q + 1u, si.x, si.y, si.z, vx, vy, vz, fx, fy, fz, pi.tag, pi.type);
+            drift_and_bin<T>(D, q + 1u, si.x, si.y, si.z, vx, vy, vz, fx, fy, fz, pi.tag, pi.type,
+                             nbond > 0);
         }
     }
 }
@@ -613,8 +626,9 @@ __global__ __launch_bounds__(256) void k_begin(DevSys<T> D, uint32_t q) {
         const int64_t slot = g * D.cap + k;
         const SRec<T> s = D.S[lay][slot];
         const PRec<T> p = D.P[lay][slot];
+        const bool bonded = D.bond_off && D.bond_off[p.tag + 1] > D.bond_off[p.tag];
         drift_and_bin<T>(D, q + 1u, s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz, p.tag,
-                         p.type);
+                         p.type, bonded);
     }
 }
 
@@ -687,6 +701,21 @@ __global__ __launch_bounds__(256) void k_gather(DevSys<T> D, uint32_t q, double 
     f[3 * i + 1] = (double)s.fy;
     f[3 * i + 2] = (double)s.fz;
     cell[i] = (int64_t)(slot / (uint32_t)D.cap);
+}
+
+// Rebuilds the full tag -> slot map of layout q (one thread per cell).
+template <typename T>
+__global__ __launch_bounds__(256) void k_slotmap(DevSys<T> D, uint32_t q) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= D.ncells) return;
+    const uint32_t lay = q & 1u;
+    const uint32_t n = min(D.count[q % 3u][g], (uint32_t)D.cap);
+    for (uint32_t k = 0; k < n; ++k) {
+        const int64_t slot = g * D.cap + k;
+        const uint32_t tag = D.P[lay][slot].tag;
+        if ((int64_t)tag < D.n) D.slot_of_tag[lay][tag] = (uint32_t)slot;
+        else atomicOr(D.err, ERR_INDEX);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
@@ -765,13 +794,15 @@ static hipError_t launch_force_v(const DevSys<T> &D, uint32_t q, int mode, hipSt
     return launch_force_g<T, BX, BY, BZ, NT, HCAP, false>(D, q, mode, st);
 }
 
-// Brick variants, selected by index: {BX, BY, BZ, threads, LDS capacity}.
+// Brick variants, selected by index: {BX, BY, BZ, threads, LDS capacity}.  The
+// capacity sits ~5 standard deviations above a rho = 3 neighbourhood's mean;
+// denser neighbourhoods are processed in chunks.
 #define DPD_VARIANTS(X)                                                                   \
-    X(0, 4, 4, 4, 256, 1024)                                                              \
-    X(1, 5, 4, 4, 256, 1152)                                                              \
-    X(2, 5, 5, 4, 320, 1344)                                                              \
-    X(3, 4, 4, 2, 128, 640)                                                               \
-    X(4, 2, 2, 2, 64, 320)
+    X(0, 4, 4, 4, 256, 800)                                                               \
+    X(1, 5, 4, 4, 256, 900)                                                               \
+    X(2, 5, 5, 4, 320, 1056)                                                              \
+    X(3, 4, 4, 2, 128, 540)                                                               \
+    X(4, 2, 2, 2, 64, 256)
 
 template <typename T>
 hipError_t launch_force(const DevSys<T> &D, uint32_t q, int mode, int variant, hipStream_t st) {
@@ -812,6 +843,8 @@ hipError_t launch_load(const DevSys<T> &D, uint32_t q, const double *x, const do
 template <typename T>
 hipError_t launch_gather(const DevSys<T> &D, uint32_t q, double *x, double *v, double *f,
                          int64_t *cell, hipStream_t st) {
+    const int64_t nc = (D.ncells + 255) / 256;
+    hipLaunchKernelGGL(k_slotmap<T>, dim3((unsigned)nc), dim3(256), 0, st, D, q);
     const int64_t nb = (D.n + 255) / 256;
     hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)nb), dim3(256), 0, st, D, q, x, v, f, cell);
     return hipGetLastError();
