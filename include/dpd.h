@@ -201,6 +201,16 @@ int dpd_variant_shape(int variant, int out[5]);
 int dpd_set_variant(dpd_system *sys, int variant);
 int dpd_autotune(dpd_system *sys, int trials, int *best_variant, double *best_ms);
 
+/*
+ * The pair noise theta_ij(s) of the random force (see the top of this file)
+ * as the step kernels compute it, for m host triples (tag_i[k], tag_j[k],
+ * s[k]) on the current device; precision selects the FP32 or FP64 Box-Muller.
+ * Writes m doubles to theta (host).  For checking and for reproducing the
+ * noise stream outside the library.  Synchronous.
+ */
+int dpd_pair_noise(uint64_t seed, int64_t m, const uint32_t *tag_i, const uint32_t *tag_j,
+                   const uint32_t *s, int precision, double *theta);
+
 /* Frees the system and its device memory (NULL is ignored). */
 void dpd_destroy(dpd_system *sys);
 

@@ -708,6 +708,35 @@ int dpd_autotune(dpd_system *s, int trials, int *best_variant, double *best_ms) 
     return DPD_OK;
 }
 
+int dpd_pair_noise(uint64_t seed, int64_t m, const uint32_t *ti, const uint32_t *tj,
+                   const uint32_t *sv, int precision, double *theta) {
+    if (m < 0 || (m > 0 && (!ti || !tj || !sv || !theta))) return fail(DPD_EINVAL, "bad arrays");
+    if (precision != DPD_PREC_FP64 && precision != DPD_PREC_MIXED)
+        return fail(DPD_EINVAL, "unknown precision %d", precision);
+    if (m == 0) return DPD_OK;
+    uint32_t *d = nullptr;
+    double *o = nullptr;
+    HIP_OK(hipMalloc((void **)&d, 3 * m * sizeof(uint32_t)));
+    hipError_t e = hipMalloc((void **)&o, m * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(DPD_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    }
+    auto run = [&]() -> int {
+        HIP_OK(hipMemcpy(d, ti, m * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d + m, tj, m * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d + 2 * m, sv, m * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_OK(launch_noise(precision == DPD_PREC_FP64, seed, m, d, d + m, d + 2 * m, o, nullptr));
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipMemcpy(theta, o, m * sizeof(double), hipMemcpyDeviceToHost));
+        return DPD_OK;
+    };
+    const int rc = run();
+    (void)hipFree(d);
+    (void)hipFree(o);
+    return rc;
+}
+
 int dpd_info(dpd_system *s, int64_t out[8]) {
     if (!s || !out) return fail(DPD_EINVAL, "null argument");
     out[0] = s->n;

@@ -134,6 +134,8 @@ __device__ __forceinline__ float t_abs(float x) { return fabsf(x); }
 // measured) for FP32; correctly rounded 1/sqrt for FP64.
 __device__ __forceinline__ float t_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double t_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float t_fma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double t_fma(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ double t_abs(double x) { return fabs(x); }
 
 // ---------------------------------------------------------------------------
@@ -148,6 +150,15 @@ __device__ __forceinline__ void mulhilo(uint32_t a, uint32_t b, uint32_t &hi, ui
     lo = (uint32_t)p;
 }
 
+// a ^ b ^ k in one VALU instruction: gfx950's three-input bitwise op with
+// the XOR truth table 0x96 (the key k is wave-uniform, so it sits in a scalar
+// register).  The compiler emits two XORs otherwise.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 // Returns the first two output words of Philox4x32 with ten rounds.
 __device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                            uint32_t k0, uint32_t k1, uint32_t &w0,
@@ -159,8 +170,8 @@ __device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2
         uint32_t hA, lA, hB, lB;
         mulhilo(MA, c0, hA, lA);
         mulhilo(MB, c2, hB, lB);
-        const uint32_t n0 = hB ^ c1 ^ k0;
-        const uint32_t n2 = hA ^ c3 ^ k1;
+        const uint32_t n0 = xor3(hB, c1, k0);
+        const uint32_t n2 = xor3(hA, c3, k1);
         c0 = n0;
         c1 = lB;
         c2 = n2;

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
     __shared__ int s_wave[NT / 64];
     __shared__ int s_flag, s_nchunk;
     __shared__ T s_a[MAXTYPES * MAXTYPES];
-    __shared__ AT s_A[HCAP + 1];     // + one far-away sentinel (IGEO)
+    __shared__ AT s_A[HCAP + 4];     // + room for the 4-wide reads past a row's end
     __shared__ LB<T> s_B[HCAP];
     // Per-lane queues of pending neighbours: LDS indices (u16) in the integer
     // frame; index plus whole-cell shift code (u32) otherwise.
@@ -311,15 +311,6 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
             const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
             if (ox < ex && oy < ey && oz < ez)
                 cz2[cell_linear(c0x + ox, c0y + oy, c0z + oz, D.nc)] = 0u;
-        }
-    }
-    if constexpr (IGEO) {
-        if (tid == 0) {
-            // At least one cell away from every own particle in each axis.
-            LAI sent;
-            sent.qx = sent.qy = sent.qz = 0u;
-            sent.tag = 0xFFFFFFFFu;
-            s_A[HCAP] = sent;
         }
     }
     __syncthreads();
@@ -418,6 +409,28 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                 const LB<T> bj = s_B[j];
                 T dx, dy, dz;
                 if constexpr (IGEO) {
+                    if (MODE != MODE_OBS) {
+                        // Cubic cells: work in offset units (u = 2^-29 h) and
+                        // rescale only r; e = d / r is unit-free.  r2 >= 1 u^2
+                        // here (the scan rejected r = 0).
+                        const T ux = (T)(int32_t)(pqx - a.qx);
+                        const T uy = (T)(int32_t)(pqy - a.qy);
+                        const T uz = (T)(int32_t)(pqz - a.qz);
+                        const T u2 = t_fma(ux, ux, t_fma(uy, uy, uz * uz));
+                        const T rinvu = t_rsqrt(u2);
+                        const T r = u2 * rinvu * hxT;
+                        const T w = (T)1 - r;
+                        const T edv = t_fma(ux, pi.vx - bj.vx,
+                                            t_fma(uy, pi.vy - bj.vy, uz * (pi.vz - bj.vz))) *
+                                      rinvu;
+                        const T th = pair_theta<T>(D.seed, pi.tag, a.tag, q);
+                        const T aij = arow[bj.type];
+                        const T c = t_fma(srdt * w, th, w * t_fma(-gamma * w, edv, aij)) * rinvu;
+                        fx = t_fma(c, ux, fx);
+                        fy = t_fma(c, uy, fy);
+                        fz = t_fma(c, uz, fz);
+                        return;
+                    }
                     dx = (T)(int32_t)(pqx - a.qx) * hxT;
                     dy = (T)(int32_t)(pqy - a.qy) * hyT;
                     dz = (T)(int32_t)(pqz - a.qz) * hzT;
@@ -487,12 +500,16 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                 const uint32_t rowcode = (uint32_t)(((dyc + 1) << 2) | ((dzc + 1) << 4));
                 for (int t = 0; __ballot(t < len); t += 4) {
                     AT a[4];
+                    const int rem = len - t;
+                    if constexpr (IGEO) {
+                        // Up to three reads past the row's end land in the next
+                        // cells or the padding; rem masks them.
+                        const AT *rowp = s_A + jb + t;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        int jj;
-                        if constexpr (IGEO) jj = t + u < len ? jb + t + u : HCAP;
-                        else jj = min(jb + t + u, max(je - 1, 0));
-                        a[u] = s_A[jj];
+                        for (int u = 0; u < 4; ++u) a[u] = rowp[u];
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) a[u] = s_A[min(jb + t + u, max(je - 1, 0))];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -507,12 +524,12 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
                                 const uint64_t r2 = (uint64_t)((int64_t)ddx * ddx +
                                                                (int64_t)ddy * ddy +
                                                                (int64_t)ddz * ddz);
-                                hit = (r2 < thr) & (a[u].tag != pi.tag);
+                                hit = (r2 < thr) & (a[u].tag != pi.tag) & (u < rem);
                             } else {
                                 const uint64_t r2m1 = (uint64_t)((int64_t)ddx * ddx - 1 +
                                                                  (int64_t)ddy * ddy +
                                                                  (int64_t)ddz * ddz);
-                                hit = r2m1 < thr1;
+                                hit = (r2m1 < thr1) & (u < rem);
                             }
                         } else {
                             const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
@@ -716,6 +733,26 @@ __global__ __launch_bounds__(256) void k_slotmap(DevSys<T> D, uint32_t q) {
         if ((int64_t)tag < D.n) D.slot_of_tag[lay][tag] = (uint32_t)slot;
         else atomicOr(D.err, ERR_INDEX);
     }
+}
+
+// theta_ij(s) for m triples, in the force precision T.
+template <typename T>
+__global__ __launch_bounds__(256) void k_noise(uint64_t seed, int64_t m, const uint32_t *ti,
+                                               const uint32_t *tj, const uint32_t *s,
+                                               double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) out[i] = (double)pair_theta<T>(seed, ti[i], tj[i], s[i]);
+}
+
+hipError_t launch_noise(int precision_fp64, uint64_t seed, int64_t m, const uint32_t *ti,
+                        const uint32_t *tj, const uint32_t *s, double *out, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    const dim3 g((unsigned)((m + 255) / 256));
+    if (precision_fp64)
+        hipLaunchKernelGGL(k_noise<double>, g, dim3(256), 0, st, seed, m, ti, tj, s, out);
+    else
+        hipLaunchKernelGGL(k_noise<float>, g, dim3(256), 0, st, seed, m, ti, tj, s, out);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {

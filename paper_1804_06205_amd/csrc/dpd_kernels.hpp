@@ -27,6 +27,8 @@ template <typename T>
 hipError_t launch_gather(const DevSys<T> &D, uint32_t q, double *x, double *v, double *f,
                          int64_t *cell, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t m, uint32_t v, hipStream_t st);
+hipError_t launch_noise(int precision_fp64, uint64_t seed, int64_t m, const uint32_t *ti,
+                        const uint32_t *tj, const uint32_t *s, double *out, hipStream_t st);
 hipError_t launch_u32_to_f64(const uint32_t *a, double *b, int64_t m, hipStream_t st);
 hipError_t launch_reduce8(const double *const *in, int64_t m, int64_t chunk, int nblocks,
                           double *out, hipStream_t st);

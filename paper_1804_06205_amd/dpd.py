@@ -75,6 +75,10 @@ SIGNATURES = {
     "dpd_set_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "dpd_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_double)]),
+    "dpd_pair_noise": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, _d]),
 }
 
 _lib = None
@@ -103,6 +107,19 @@ def variants() -> list:
         a = (ctypes.c_int * 5)()
         _check(lib().dpd_variant_shape(v, a))
         out.append(tuple(a))
+    return out
+
+
+def pair_noise(seed: int, ti, tj, s, precision: str = "mixed") -> np.ndarray:
+    """theta_ij(s) as the step kernels compute it, for arrays of triples."""
+    u32 = ctypes.POINTER(ctypes.c_uint32)
+    ti = np.ascontiguousarray(ti, np.uint32)
+    tj = np.ascontiguousarray(tj, np.uint32)
+    s = np.ascontiguousarray(np.broadcast_to(s, ti.shape), np.uint32)
+    out = np.zeros(ti.shape[0])
+    _check(lib().dpd_pair_noise(seed, ti.shape[0], _p(ti, u32), _p(tj, u32), _p(s, u32),
+                                PREC_FP64 if precision == "fp64" else PREC_MIXED,
+                                _p(out, _d)))
     return out
 
 

@@ -351,3 +351,21 @@ def test_autotune_leaves_the_state_unchanged():
         got = g3.get_state()
     for a, b in zip(got[:3], ref[:3]):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_device_pair_noise_matches_oracle(precision):
+    # The kernels' Philox4x32-10 + Box-Muller against the oracle's independent
+    # implementation: FP32 agrees to its rounding of theta (|theta| <= 5.8),
+    # FP64 to ~1e-13.
+    rng = np.random.default_rng(8)
+    m = 200_000
+    ti = rng.integers(0, 2 ** 32, size=m, dtype=np.uint64).astype(np.uint32)
+    tj = rng.integers(0, 2 ** 32, size=m, dtype=np.uint64).astype(np.uint32)
+    s = rng.integers(0, 2 ** 32, size=m, dtype=np.uint64).astype(np.uint32)
+    seed = 0x0123456789ABCDEF
+    got = dpd.pair_noise(seed, ti, tj, s, precision)
+    ref = oracle.pair_noise_batch(seed, ti, tj, s)
+    tol = 1.5e-6 if precision == "mixed" else 1e-12
+    assert np.abs(got - ref).max() <= tol
+    np.testing.assert_array_equal(dpd.pair_noise(seed, tj, ti, s, precision), got)
