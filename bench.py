@@ -42,6 +42,8 @@ def parse():
                     choices=["fluid_L96", "fluid_L10", "melt_L32", "peptide_L40"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--variant", type=int, default=None,
+                    help="use this brick variant instead of autotuning")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps (for rocprofv3), print nothing else")
     return ap.parse_args()
@@ -86,6 +88,8 @@ def main():
     w = make_workload(args.workload)
     stream = torch.cuda.Stream()
     g = dpd.System.from_workload(w, stream=stream)
+    if args.variant is not None:
+        g.set_variant(args.variant)
     if args.profile_steps:
         g.step(args.profile_steps)
         g.sync()
@@ -96,7 +100,10 @@ def main():
     g.sync()
     # The autotuner picks the brick shape (every shape gives bitwise the same
     # trajectory); it only times kernels on the current state.
-    variant, tuned_ms = g.autotune(3)
+    if args.variant is None:
+        variant, _ = g.autotune(3)
+    else:
+        variant = args.variant
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)

@@ -65,7 +65,8 @@ enum dpd_status {
     DPD_ERANGE = -6,     /* bond tag out of range or i == j, or bond length >= L/2     */
     DPD_ESTATE = -7,     /* parameters or bonds changed after the first step, or a call
                             before dpd_set_params                                      */
-    DPD_EBUSY = -8,      /* batch full or over its memory budget                       */
+    DPD_EBUSY = -8,      /* batch full or over its memory budget, or the system is
+                            resident in a batch                                        */
     DPD_ECAPACITY = -9   /* a cell held more particles than its slots (local density far
                             above the box average); recreate with a larger cell_capacity */
 };
@@ -211,8 +212,62 @@ int dpd_autotune(dpd_system *sys, int trials, int *best_variant, double *best_ms
 int dpd_pair_noise(uint64_t seed, int64_t m, const uint32_t *tag_i, const uint32_t *tag_j,
                    const uint32_t *s, int precision, double *theta);
 
-/* Frees the system and its device memory (NULL is ignored). */
+/* Frees the system and its device memory (NULL is ignored).  A system still
+ * resident in a batch is retired from it first. */
 void dpd_destroy(dpd_system *sys);
+
+/* Device bytes that dpd_create (plus dpd_add_bonds with nbonds records) will
+ * allocate for such a system; equals out[3] of dpd_info after the first step.
+ * For admission decisions before a system is created. */
+int dpd_footprint_bytes(const double L[3], int64_t n, int64_t nbonds, int precision,
+                        int cell_capacity, int64_t *bytes);
+
+/*
+ * Replica batches.  A batch advances many independent resident systems
+ * (replicas: each its own box, parameters, seed and bonds) together: every
+ * pass of a step is one launch over the work items of all replicas, and a
+ * window of K steps is one captured HIP graph, replayed while the set of
+ * replicas stays the same.  Each replica follows exactly the trajectory
+ * dpd_step would give it alone (bit for bit).  Batches hold mixed-precision
+ * systems with cubic cells.
+ *
+ *   dpd_batch_create(out, budget_bytes, max_replicas, hip_stream, variant)
+ *       budget_bytes  cap on the summed device bytes (dpd_info out[3]) of the
+ *                     resident systems; max_replicas  number of slots (1..65536);
+ *       hip_stream    stream for the batch's work (NULL = library-owned);
+ *       variant       brick variant of the batched pair pass (-1 = 2x2x2).
+ *   dpd_batch_admit(b, sys, nsteps, &slot)
+ *       makes sys resident with a target of nsteps more steps.  Computes the
+ *       initial force if needed and waits for the system's stream and the
+ *       batch.  DPD_EBUSY if the budget or the slots would be exceeded.  While
+ *       resident, every call on sys except dpd_info and dpd_destroy fails
+ *       with DPD_EBUSY.
+ *   dpd_batch_advance(b, K)
+ *       enqueues one window: every resident replica advances min(K, steps
+ *       left) steps.  Asynchronous.
+ *   dpd_batch_poll(b, done, max_done, &ndone)
+ *       waits for the enqueued windows, then lists (once each) the slots whose
+ *       replica has reached its target or hit a device error (the error then
+ *       surfaces on the system after retirement).
+ *   dpd_batch_retire(b, slot)
+ *       waits for the batch and hands the system back (usable as before, its
+ *       step counter advanced); the slot and its bytes are freed.
+ *   dpd_batch_info(b, out[6])
+ *       resident replicas, bytes used, budget, graph captures, windows, variant.
+ *   dpd_batch_destroy(b)
+ *       retires every resident replica and frees the batch.
+ * Calls on one batch must not overlap (not thread-safe).
+ */
+typedef struct dpd_batch dpd_batch;
+
+int dpd_batch_create(dpd_batch **out, int64_t budget_bytes, int max_replicas, void *hip_stream,
+                     int variant);
+int dpd_batch_admit(dpd_batch *b, dpd_system *sys, int64_t nsteps, int *slot);
+int dpd_batch_advance(dpd_batch *b, int64_t K);
+int dpd_batch_poll(dpd_batch *b, int *done, int max_done, int *ndone);
+int dpd_batch_retire(dpd_batch *b, int slot);
+int dpd_batch_info(dpd_batch *b, int64_t out[6]);
+void dpd_batch_destroy(dpd_batch *b);
 
 #ifdef __cplusplus
 }

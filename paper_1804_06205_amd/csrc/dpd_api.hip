@@ -40,7 +40,27 @@ int fail(int code, const char *fmt, ...) {
 
 template <typename T> size_t prec_size() { return sizeof(T); }
 
+// Device bytes dpd_create allocates for a system (and dpd_add_bonds adds at
+// the first step), in the order of the allocations below.
+int64_t footprint(int prec, int64_t ncells, int64_t n, int64_t nb, int cap) {
+    const int64_t psz = prec == DPD_PREC_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>);
+    const int64_t ssz = prec == DPD_PREC_FP64 ? sizeof(SRec<double>) : sizeof(SRec<float>);
+    const int64_t slots = ncells * cap;
+    const int64_t red_blocks = std::min<int64_t>(256, (n + 1023) / 1024);
+    int64_t b = 2 * (slots * psz + slots * ssz + n * (int64_t)sizeof(uint32_t));
+    b += 3 * ncells * (int64_t)sizeof(uint32_t);
+    b += 256 * (int64_t)sizeof(double) + (int64_t)sizeof(uint32_t);
+    b += 9 * n * (int64_t)sizeof(double) + n * (int64_t)sizeof(int64_t) + n;
+    b += 9 * n * (int64_t)sizeof(double) + n * (int64_t)sizeof(uint32_t);
+    b += 8 * (int64_t)sizeof(double *) + red_blocks * 8 * (int64_t)sizeof(double);
+    if (nb > 0)
+        b += (n + 1) * (int64_t)sizeof(uint32_t) + 2 * nb * (int64_t)sizeof(BondEnt<double>);
+    return b;
+}
+
 }  // namespace
+
+struct dpd_batch;
 
 struct dpd_system {
     int prec = DPD_PREC_MIXED;
@@ -84,6 +104,8 @@ struct dpd_system {
 
     int64_t t = 0;                  // state index of the resting state
     bool force_valid = false;
+    dpd_batch *batch = nullptr;     // the batch this system is resident in, if any
+    int batch_slot = -1;
     int variant = 0;
     int sticky = DPD_OK;
     std::string sticky_msg;
@@ -288,9 +310,12 @@ bool all_finite(const double *p, int64_t m) {
 
 int check_usable(dpd_system *s) {
     if (!s) return fail(DPD_EINVAL, "null system");
+    if (s->batch) return fail(DPD_EBUSY, "the system is resident in a batch; retire it first");
     if (s->sticky != DPD_OK) return fail(s->sticky, "%s", s->sticky_msg.c_str());
     return DPD_OK;
 }
+
+int batch_detach(dpd_batch *b, int slot);
 
 }  // namespace
 
@@ -527,6 +552,7 @@ int dpd_step_profiled(dpd_system *s, int64_t nsteps, dpd_kernel_times *out) {
 
 int dpd_sync(dpd_system *s) {
     if (!s) return fail(DPD_EINVAL, "null system");
+    if (s->batch) return fail(DPD_EBUSY, "the system is resident in a batch; retire it first");
     return check_device(s);
 }
 
@@ -752,10 +778,402 @@ int dpd_info(dpd_system *s, int64_t out[8]) {
 
 void dpd_destroy(dpd_system *s) {
     if (!s) return;
+    if (s->batch) (void)batch_detach(s->batch, s->batch_slot);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     free_all(s);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Replica batches: many resident systems advanced by shared launches, one
+// captured HIP graph per window of K steps.
+// ---------------------------------------------------------------------------
+struct dpd_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t budget = 0, used = 0;
+    int max_slots = 0;
+    int variant = 4;
+    int bx = 2, by = 2, bz = 2;
+
+    std::vector<dpd_system *> sys;     // per slot (null = free)
+    std::vector<uint32_t> t0, target;  // host mirror of the device counters
+    std::vector<uint8_t> reported;
+    std::vector<uint32_t> err;
+
+    // Device tables (fixed addresses for the life of the batch, except the
+    // work lists, which grow and then force a re-capture).
+    BatchEnt *tab = nullptr;
+    uint32_t *t0_dev = nullptr, *target_dev = nullptr, *status_dev = nullptr;
+    int *nwork_dev = nullptr;
+    BatchWork *wf = nullptr, *wb = nullptr;
+    int cap_wf = 0, cap_wb = 0;
+
+    // Pinned host staging.
+    uint32_t *status_h = nullptr;
+    BatchEnt *tab_h = nullptr;
+    uint32_t *ctr_h = nullptr;           // t0 then target, 2 * max_slots
+    int *nwork_h = nullptr;
+    std::vector<BatchWork> wf_v, wb_v;
+    BatchWork *wf_h = nullptr, *wb_h = nullptr;
+    int cap_wf_h = 0, cap_wb_h = 0;
+
+    bool dirty = true;        // host tables changed since the last upload
+    bool inflight = false;    // a window was enqueued since the last refresh
+    int n_force = 0, n_begin = 0;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_K = 0, graph_wf = 0, graph_wb = 0;
+    const BatchWork *graph_wf_ptr = nullptr, *graph_wb_ptr = nullptr;
+    int64_t captures = 0, windows = 0;
+    hipEvent_t done = nullptr;
+};
+
+namespace {
+
+void batch_free(dpd_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    void *dptr[] = {b->tab, b->t0_dev, b->target_dev, b->status_dev, b->nwork_dev, b->wf, b->wb};
+    for (void *p : dptr)
+        if (p) (void)hipFree(p);
+    void *hptr[] = {b->status_h, b->tab_h, b->ctr_h, b->nwork_h, b->wf_h, b->wb_h};
+    for (void *p : hptr)
+        if (p) (void)hipHostFree(p);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+// Waits for enqueued windows and takes the device counters into the host mirror.
+int batch_refresh(dpd_batch *b) {
+    HIP_OK(hipStreamSynchronize(b->stream));
+    if (!b->inflight) return DPD_OK;
+    for (int k = 0; k < b->max_slots; ++k) {
+        if (!b->sys[k]) continue;
+        b->t0[k] = b->status_h[2 * k];
+        b->err[k] = b->status_h[2 * k + 1];
+        b->sys[k]->t = b->t0[k];
+    }
+    b->inflight = false;
+    return DPD_OK;
+}
+
+template <typename P> int grow_pinned(P **p, int *cap, int need) {
+    if (need <= *cap) return DPD_OK;
+    int c = std::max(need, 2 * *cap);
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipHostMalloc((void **)p, (size_t)c * sizeof(P), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(DPD_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+    *cap = c;
+    return DPD_OK;
+}
+
+template <typename P> int grow_device(P **p, int *cap, int need) {
+    if (need <= *cap) return DPD_OK;
+    int c = std::max(need, 2 * *cap);
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc((void **)p, (size_t)c * sizeof(P));
+    if (e != hipSuccess) return fail(DPD_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    *cap = c;
+    return DPD_OK;
+}
+
+// Rebuilds the work lists and uploads every table (the stream is idle).
+int batch_upload(dpd_batch *b) {
+    b->wf_v.clear();
+    b->wb_v.clear();
+    for (int k = 0; k < b->max_slots; ++k) {
+        dpd_system *s = b->sys[k];
+        if (!s || b->t0[k] >= b->target[k]) continue;
+        const int nbr = b->tab_h[k].nbx * b->tab_h[k].nby * ((s->nc[2] + b->bz - 1) / b->bz);
+        for (int i = 0; i < nbr; ++i) b->wf_v.push_back(BatchWork{(uint32_t)k, (uint32_t)i});
+        const int nblk = (int)((s->ncells + 255) / 256);
+        for (int i = 0; i < nblk; ++i) b->wb_v.push_back(BatchWork{(uint32_t)k, (uint32_t)i});
+    }
+    b->n_force = (int)b->wf_v.size();
+    b->n_begin = (int)b->wb_v.size();
+    if (int rc = grow_device(&b->wf, &b->cap_wf, std::max(1, b->n_force))) return rc;
+    if (int rc = grow_device(&b->wb, &b->cap_wb, std::max(1, b->n_begin))) return rc;
+    if (int rc = grow_pinned(&b->wf_h, &b->cap_wf_h, std::max(1, b->n_force))) return rc;
+    if (int rc = grow_pinned(&b->wb_h, &b->cap_wb_h, std::max(1, b->n_begin))) return rc;
+    std::copy(b->wf_v.begin(), b->wf_v.end(), b->wf_h);
+    std::copy(b->wb_v.begin(), b->wb_v.end(), b->wb_h);
+    for (int k = 0; k < b->max_slots; ++k) {
+        b->ctr_h[k] = b->t0[k];
+        b->ctr_h[b->max_slots + k] = b->target[k];
+    }
+    b->nwork_h[0] = b->n_force;
+    b->nwork_h[1] = b->n_begin;
+    b->nwork_h[2] = b->max_slots;
+    const size_t ms = (size_t)b->max_slots;
+    HIP_OK(hipMemcpyAsync(b->tab, b->tab_h, ms * sizeof(BatchEnt), hipMemcpyHostToDevice,
+                          b->stream));
+    HIP_OK(hipMemcpyAsync(b->t0_dev, b->ctr_h, ms * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          b->stream));
+    HIP_OK(hipMemcpyAsync(b->target_dev, b->ctr_h + ms, ms * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, b->stream));
+    HIP_OK(hipMemcpyAsync(b->nwork_dev, b->nwork_h, 3 * sizeof(int), hipMemcpyHostToDevice,
+                          b->stream));
+    if (b->n_force)
+        HIP_OK(hipMemcpyAsync(b->wf, b->wf_h, (size_t)b->n_force * sizeof(BatchWork),
+                              hipMemcpyHostToDevice, b->stream));
+    if (b->n_begin)
+        HIP_OK(hipMemcpyAsync(b->wb, b->wb_h, (size_t)b->n_begin * sizeof(BatchWork),
+                              hipMemcpyHostToDevice, b->stream));
+    // The pinned staging must not change before the copies are done.
+    HIP_OK(hipStreamSynchronize(b->stream));
+    b->dirty = false;
+    return DPD_OK;
+}
+
+int batch_capture(dpd_batch *b, int K) {
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    BatchDev B;
+    B.tab = b->tab;
+    B.t0 = b->t0_dev;
+    B.target = b->target_dev;
+    B.wf = b->wf;
+    B.wb = b->wb;
+    B.nwork = b->nwork_dev;
+    B.status = b->status_dev;
+    HIP_OK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_batch_window(B, b->variant, K, b->cap_wf, b->cap_wb, b->max_slots,
+                                       b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(DPD_EDEVICE, "capturing the batch window failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    HIP_OK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_K = K;
+    b->graph_wf = b->cap_wf;
+    b->graph_wb = b->cap_wb;
+    b->graph_wf_ptr = b->wf;
+    b->graph_wb_ptr = b->wb;
+    ++b->captures;
+    return DPD_OK;
+}
+
+int batch_detach(dpd_batch *b, int slot) {
+    if (int rc = batch_refresh(b)) return rc;
+    dpd_system *s = b->sys[slot];
+    s->t = b->t0[slot];
+    s->batch = nullptr;
+    s->batch_slot = -1;
+    b->used -= (int64_t)s->bytes;
+    b->sys[slot] = nullptr;
+    b->t0[slot] = b->target[slot] = 0;
+    b->err[slot] = 0;
+    b->reported[slot] = 0;
+    std::memset(&b->tab_h[slot], 0, sizeof(BatchEnt));
+    b->dirty = true;
+    return DPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpd_footprint_bytes(const double L[3], int64_t n, int64_t nbonds, int precision,
+                        int cell_capacity, int64_t *bytes) {
+    if (!L || !bytes) return fail(DPD_EINVAL, "null argument");
+    if (n < 2 || nbonds < 0) return fail(DPD_EINVAL, "bad sizes");
+    if (precision != DPD_PREC_FP64 && precision != DPD_PREC_MIXED)
+        return fail(DPD_EINVAL, "unknown precision %d", precision);
+    if (cell_capacity < 0 || cell_capacity > 1024)
+        return fail(DPD_EINVAL, "cell_capacity must be in 0..1024");
+    int64_t nc = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(L[k]) || L[k] < 3.0) return fail(DPD_EBOX, "box edge below 3");
+        nc *= (int64_t)std::floor(L[k]);
+    }
+    *bytes = footprint(precision, nc, n, nbonds, cell_capacity ? cell_capacity : 32);
+    return DPD_OK;
+}
+
+int dpd_batch_create(dpd_batch **out, int64_t budget_bytes, int max_replicas, void *hip_stream,
+                     int variant) {
+    g_err.clear();
+    if (!out) return fail(DPD_EINVAL, "null argument");
+    *out = nullptr;
+    if (budget_bytes <= 0) return fail(DPD_EINVAL, "budget must be > 0");
+    if (max_replicas < 1 || max_replicas > 65536)
+        return fail(DPD_EINVAL, "max_replicas must be in 1..65536");
+    if (variant < -1 || variant >= force_variant_count())
+        return fail(DPD_EINVAL, "bad variant %d", variant);
+    dpd_batch *b = new (std::nothrow) dpd_batch();
+    if (!b) return fail(DPD_ENOMEM, "host allocation failed");
+    b->budget = budget_bytes;
+    b->max_slots = max_replicas;
+    b->variant = variant < 0 ? 4 : variant;
+    int shape[5];
+    force_variant_shape(b->variant, shape);
+    b->bx = shape[0];
+    b->by = shape[1];
+    b->bz = shape[2];
+    const size_t ms = (size_t)max_replicas;
+    b->sys.assign(ms, nullptr);
+    b->t0.assign(ms, 0);
+    b->target.assign(ms, 0);
+    b->reported.assign(ms, 0);
+    b->err.assign(ms, 0);
+    auto setup = [&]() -> int {
+        if (hip_stream) {
+            b->stream = (hipStream_t)hip_stream;
+        } else {
+            HIP_OK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+            b->own_stream = true;
+        }
+        HIP_OK(hipMalloc((void **)&b->tab, ms * sizeof(BatchEnt)));
+        HIP_OK(hipMalloc((void **)&b->t0_dev, ms * sizeof(uint32_t)));
+        HIP_OK(hipMalloc((void **)&b->target_dev, ms * sizeof(uint32_t)));
+        HIP_OK(hipMalloc((void **)&b->status_dev, 2 * ms * sizeof(uint32_t)));
+        HIP_OK(hipMalloc((void **)&b->nwork_dev, 3 * sizeof(int)));
+        HIP_OK(hipHostMalloc((void **)&b->status_h, 2 * ms * sizeof(uint32_t),
+                             hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&b->tab_h, ms * sizeof(BatchEnt), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&b->ctr_h, 2 * ms * sizeof(uint32_t), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&b->nwork_h, 3 * sizeof(int), hipHostMallocDefault));
+        std::memset(b->tab_h, 0, ms * sizeof(BatchEnt));
+        std::memset(b->status_h, 0, 2 * ms * sizeof(uint32_t));
+        HIP_OK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+        return batch_upload(b);
+    };
+    if (int rc = setup()) {
+        std::string msg = g_err;
+        batch_free(b);
+        delete b;
+        return fail(rc, "%s", msg.c_str());
+    }
+    *out = b;
+    return DPD_OK;
+}
+
+int dpd_batch_admit(dpd_batch *b, dpd_system *s, int64_t nsteps, int *slot) {
+    if (!b || !s) return fail(DPD_EINVAL, "null argument");
+    if (s->batch) return fail(DPD_EINVAL, "the system is already resident in a batch");
+    if (int rc = check_usable(s)) return rc;
+    if (nsteps < 0) return fail(DPD_EINVAL, "negative step count");
+    if (s->prec != DPD_PREC_MIXED)
+        return fail(DPD_EINVAL, "batches hold mixed-precision systems only");
+    if (!(s->h[0] == s->h[1] && s->h[0] == s->h[2]))
+        return fail(DPD_EINVAL, "batches need cubic cells (equal cell edges on all axes)");
+    if (s->t + nsteps >= ((int64_t)1 << 32))
+        return fail(DPD_EINVAL, "step counter would pass 2^32");
+    if (int rc = freeze(s)) return rc;
+    if (int rc = ensure_force(s)) return rc;
+    if (int rc = check_device(s)) return rc;   // also waits for the system's own stream
+    if (int rc = batch_refresh(b)) return rc;
+    if (b->used + (int64_t)s->bytes > b->budget)
+        return fail(DPD_EBUSY, "admitting %lld bytes would exceed the batch budget (%lld of %lld used)",
+                    (long long)s->bytes, (long long)b->used, (long long)b->budget);
+    int k = 0;
+    while (k < b->max_slots && b->sys[k]) ++k;
+    if (k == b->max_slots) return fail(DPD_EBUSY, "all %d batch slots are taken", b->max_slots);
+    BatchEnt e;
+    std::memset(&e, 0, sizeof e);
+    e.D = make_dev<float>(s);
+    e.nbx = (s->nc[0] + b->bx - 1) / b->bx;
+    e.nby = (s->nc[1] + b->by - 1) / b->by;
+    const double lim = 536870912.0 / s->h[0];
+    e.thr = (uint64_t)std::ceil(lim * lim);
+    b->tab_h[k] = e;
+    b->sys[k] = s;
+    b->t0[k] = (uint32_t)s->t;
+    b->target[k] = (uint32_t)(s->t + nsteps);
+    b->err[k] = 0;
+    b->reported[k] = 0;
+    b->used += (int64_t)s->bytes;
+    s->batch = b;
+    s->batch_slot = k;
+    b->dirty = true;
+    if (slot) *slot = k;
+    return DPD_OK;
+}
+
+int dpd_batch_advance(dpd_batch *b, int64_t K) {
+    if (!b) return fail(DPD_EINVAL, "null batch");
+    if (K < 1 || K > 100000) return fail(DPD_EINVAL, "window length must be in 1..100000");
+    if (b->dirty) {
+        if (int rc = batch_refresh(b)) return rc;
+        if (int rc = batch_upload(b)) return rc;
+    }
+    if (b->n_force == 0) return DPD_OK;   // nothing left to step
+    if (!b->exec || b->graph_K != K || b->graph_wf != b->cap_wf || b->graph_wb != b->cap_wb ||
+        b->graph_wf_ptr != b->wf || b->graph_wb_ptr != b->wb) {
+        HIP_OK(hipStreamSynchronize(b->stream));
+        if (int rc = batch_capture(b, (int)K)) return rc;
+    }
+    HIP_OK(hipGraphLaunch(b->exec, b->stream));
+    HIP_OK(hipMemcpyAsync(b->status_h, b->status_dev, 2 * (size_t)b->max_slots * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, b->stream));
+    HIP_OK(hipEventRecord(b->done, b->stream));
+    b->inflight = true;
+    ++b->windows;
+    // Replicas that reach their target keep their (now idle) work items until
+    // the next admission or retirement rebuilds the lists.
+    return DPD_OK;
+}
+
+int dpd_batch_poll(dpd_batch *b, int *done, int max_done, int *ndone) {
+    if (!b || !ndone || (max_done > 0 && !done)) return fail(DPD_EINVAL, "null argument");
+    *ndone = 0;
+    if (int rc = batch_refresh(b)) return rc;
+    for (int k = 0; k < b->max_slots && *ndone < max_done; ++k) {
+        if (!b->sys[k] || b->reported[k]) continue;
+        if (b->t0[k] >= b->target[k] || b->err[k]) {
+            b->reported[k] = 1;
+            done[(*ndone)++] = k;
+        }
+    }
+    return DPD_OK;
+}
+
+int dpd_batch_retire(dpd_batch *b, int slot) {
+    if (!b) return fail(DPD_EINVAL, "null batch");
+    if (slot < 0 || slot >= b->max_slots || !b->sys[slot])
+        return fail(DPD_EINVAL, "slot %d holds no replica", slot);
+    return batch_detach(b, slot);
+}
+
+int dpd_batch_info(dpd_batch *b, int64_t out[6]) {
+    if (!b || !out) return fail(DPD_EINVAL, "null argument");
+    int64_t res = 0;
+    for (dpd_system *s : b->sys) res += s ? 1 : 0;
+    out[0] = res;
+    out[1] = b->used;
+    out[2] = b->budget;
+    out[3] = b->captures;
+    out[4] = b->windows;
+    out[5] = b->variant;
+    return DPD_OK;
+}
+
+void dpd_batch_destroy(dpd_batch *b) {
+    if (!b) return;
+    for (int k = 0; k < b->max_slots; ++k)
+        if (b->sys[k]) (void)batch_detach(b, k);
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    delete b;
 }
 
 }  // extern "C"

@@ -242,9 +242,12 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, co
     }
 }
 
+// Forces of state q for brick b (of nbx x nby x .. bricks).  fin (MODE_FUSED
+// only) ends the step in place like MODE_FINISH instead of moving on to state
+// q + 1; replicas of a batch use it for their last step of a window.
 template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO>
-__global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, int nby,
-                                              int nbricks, uint64_t thr) {
+__device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int b, int nbx,
+                                            int nby, uint64_t thr, bool fin) {
     constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
     constexpr int NHC = HX * HY * HZ;
     constexpr int NOC = BX * BY * BZ;
@@ -280,7 +283,6 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
     __syncthreads();
     if (s_flag) return;
 
-    const int b = xcd_brick(blockIdx.x, nbricks);
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int c0x = bx * BX, c0y = by * BY, c0z = bz * BZ;
     const int ex = min(BX, D.nc[0] - c0x), ey = min(BY, D.nc[1] - c0y), ez = min(BZ, D.nc[2] - c0z);
@@ -616,7 +618,7 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
         const T vx = si.vx + hdt * (si.fx + fx);
         const T vy = si.vy + hdt * (si.fy + fy);
         const T vz = si.vz + hdt * (si.fz + fz);
-        if (MODE == MODE_FINISH) {
+        if (MODE == MODE_FINISH || fin) {
             sp->vx = vx;
             sp->vy = vy;
             sp->vz = vz;
@@ -630,11 +632,17 @@ __global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, 
     }
 }
 
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO>
+__global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, int nby,
+                                              int nbricks, uint64_t thr) {
+    force_brick<T, BX, BY, BZ, NT, HCAP, MODE, IGEO>(D, q, xcd_brick(blockIdx.x, nbricks), nbx,
+                                                     nby, thr, false);
+}
+
 // begin: integrate-1 and binning of every particle of resting state q; one
-// thread per cell of layout q.
+// thread per cell g of layout q.
 template <typename T>
-__global__ __launch_bounds__(256) void k_begin(DevSys<T> D, uint32_t q) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void begin_cell(const DevSys<T> &D, uint32_t q, int64_t g) {
     if (g >= D.ncells) return;
     const uint32_t lay = q & 1u;
     D.count[(q + 2u) % 3u][g] = 0u;
@@ -647,6 +655,54 @@ __global__ __launch_bounds__(256) void k_begin(DevSys<T> D, uint32_t q) {
         drift_and_bin<T>(D, q + 1u, s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz, p.tag,
                          p.type, bonded);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_begin(DevSys<T> D, uint32_t q) {
+    begin_cell<T>(D, q, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernels.  Window step k of a replica with window start t0 computes
+// the forces of state q = t0 + k + 1 (the state begin or the previous pass
+// moved it to), exactly as dpd_step does, so a replica follows the same
+// trajectory bit for bit whatever else shares the batch.
+// ---------------------------------------------------------------------------
+// The replica table is read in place (a copy would be indexed dynamically and
+// land in scratch); it is never written during a window, which the restrict
+// qualifier tells the compiler, so its fields stay uniform scalar loads.
+template <int BX, int BY, int BZ, int NT, int HCAP>
+__global__ __launch_bounds__(NT) void k_force_batch(const BatchEnt *__restrict__ tab,
+                                                    BatchDev B, uint32_t k, uint32_t last) {
+    const int nw = B.nwork[0];
+    if ((int)blockIdx.x >= nw) return;
+    const BatchWork w = B.wf[xcd_brick(blockIdx.x, nw)];
+    const uint32_t t0 = B.t0[w.slot], tgt = B.target[w.slot];
+    if (tgt - t0 <= k) return;     // the replica reached its target earlier
+    const uint32_t q = t0 + k + 1u;
+    const BatchEnt &E = tab[w.slot];
+    force_brick<float, BX, BY, BZ, NT, HCAP, MODE_FUSED, true>(E.D, q, (int)w.item, E.nbx, E.nby,
+                                                               E.thr, q == tgt || last != 0u);
+}
+
+__global__ __launch_bounds__(256) void k_begin_batch(const BatchEnt *__restrict__ tab,
+                                                     BatchDev B) {
+    if ((int)blockIdx.x >= B.nwork[1]) return;
+    const BatchWork w = B.wb[blockIdx.x];
+    const uint32_t t0 = B.t0[w.slot];
+    if (t0 >= B.target[w.slot]) return;
+    begin_cell<float>(tab[w.slot].D, t0, (int64_t)w.item * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_end_batch(BatchDev B, uint32_t K) {
+    const int slot = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (slot >= B.nwork[2]) return;
+    const uint32_t t0 = B.t0[slot], tgt = B.target[slot];
+    const uint32_t t = t0 + min(K, tgt - t0);
+    const uint32_t *err = B.tab[slot].D.err;
+    B.t0[slot] = t;
+    B.status[2 * slot] = t;
+    B.status[2 * slot + 1] = err ? *err : 0u;
 }
 
 // load: bins host-provided state (tag order) into the layout of state q.
@@ -861,6 +917,31 @@ void force_variant_shape(int variant, int out[5]) {
 #undef DPD_ROW
     };
     for (int k = 0; k < 5; ++k) out[k] = t[variant][k];
+}
+
+template <int BX, int BY, int BZ, int NT, int HCAP>
+static hipError_t launch_batch_v(const BatchDev &B, int K, int cap_force, int cap_begin,
+                                 int cap_slots, hipStream_t st) {
+    if (cap_begin > 0)
+        hipLaunchKernelGGL(k_begin_batch, dim3(cap_begin), dim3(256), 0, st, B.tab, B);
+    for (int k = 0; k < K && cap_force > 0; ++k)
+        hipLaunchKernelGGL((k_force_batch<BX, BY, BZ, NT, HCAP>), dim3(cap_force), dim3(NT), 0, st,
+                           B.tab, B, (uint32_t)k, (uint32_t)(k == K - 1));
+    hipLaunchKernelGGL(k_end_batch, dim3((cap_slots + 255) / 256), dim3(256), 0, st, B,
+                       (uint32_t)K);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_window(const BatchDev &B, int variant, int K, int cap_force,
+                               int cap_begin, int cap_slots, hipStream_t st) {
+    if (K < 1 || cap_slots < 1) return hipErrorInvalidValue;
+    switch (variant) {
+#define DPD_CASE(i, bx, by, bz, nt, hc)                                                   \
+    case i: return launch_batch_v<bx, by, bz, nt, hc>(B, K, cap_force, cap_begin, cap_slots, st);
+        DPD_VARIANTS(DPD_CASE)
+#undef DPD_CASE
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T> hipError_t launch_begin(const DevSys<T> &D, uint32_t q, hipStream_t st) {

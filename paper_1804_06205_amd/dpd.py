@@ -79,6 +79,17 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, _d]),
+    "dpd_footprint_bytes": (ctypes.c_int, [_d, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                           ctypes.c_int, _i64]),
+    "dpd_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int64, ctypes.c_int, _vp,
+                                        ctypes.c_int]),
+    "dpd_batch_admit": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int)]),
+    "dpd_batch_advance": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "dpd_batch_poll": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]),
+    "dpd_batch_retire": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dpd_batch_info": (ctypes.c_int, [_vp, _i64]),
+    "dpd_batch_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -121,6 +132,17 @@ def pair_noise(seed: int, ti, tj, s, precision: str = "mixed") -> np.ndarray:
                                 PREC_FP64 if precision == "fp64" else PREC_MIXED,
                                 _p(out, _d)))
     return out
+
+
+def footprint_bytes(L, n: int, nbonds: int = 0, precision: str = "mixed",
+                    cell_capacity: int = 0) -> int:
+    """Device bytes a system of this shape will hold (dpd_info's device_bytes)."""
+    Lv = _f64(L, (3,))
+    out = ctypes.c_int64()
+    _check(lib().dpd_footprint_bytes(_p(Lv, _d), n, nbonds,
+                                     PREC_FP64 if precision == "fp64" else PREC_MIXED,
+                                     cell_capacity, ctypes.byref(out)))
+    return out.value
 
 
 def last_error() -> str:
@@ -267,3 +289,62 @@ class System:
         _check(lib().dpd_info(self._h, _p(out, _i64)))
         keys = ("n", "ncells", "cell_capacity", "device_bytes", "nx", "ny", "nz", "precision")
         return dict(zip(keys, (int(v) for v in out)))
+
+
+class Batch:
+    """A replica batch (dpd_batch_*): resident systems advanced together, one
+    captured HIP graph per window of K steps."""
+
+    def __init__(self, budget_bytes: int, max_replicas: int = 1024, stream=None,
+                 variant: int = -1):
+        self._h = None
+        h = _vp()
+        _check(lib().dpd_batch_create(ctypes.byref(h), int(budget_bytes), max_replicas,
+                                      _stream_handle(stream), variant))
+        self._h = h
+        self.max_replicas = max_replicas
+        self._members = {}      # slot -> System (keeps them alive while resident)
+
+    def admit(self, system: System, nsteps: int) -> int:
+        slot = ctypes.c_int()
+        _check(lib().dpd_batch_admit(self._h, system._h, nsteps, ctypes.byref(slot)))
+        self._members[slot.value] = system
+        return slot.value
+
+    def advance(self, K: int):
+        _check(lib().dpd_batch_advance(self._h, K))
+
+    def poll(self) -> list:
+        """Waits for the enqueued windows; slots that finished since the last poll."""
+        out = (ctypes.c_int * self.max_replicas)()
+        nd = ctypes.c_int()
+        _check(lib().dpd_batch_poll(self._h, out, self.max_replicas, ctypes.byref(nd)))
+        return list(out[:nd.value])
+
+    def retire(self, slot: int) -> System:
+        _check(lib().dpd_batch_retire(self._h, slot))
+        return self._members.pop(slot)
+
+    def info(self) -> dict:
+        out = np.zeros(6, np.int64)
+        _check(lib().dpd_batch_info(self._h, _p(out, _i64)))
+        keys = ("resident", "bytes_used", "budget", "captures", "windows", "variant")
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.dpd_batch_destroy(self._h)
+        self._h = None
+        self._members.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,186 @@
+"""Replica batches (dpd_batch_*) and the serving loop on the GPU.
+
+A replica advanced inside a batch, among replicas of other sizes, admitted at
+other times and stepped by windows that do not divide its step count, must end
+bit for bit where dpd_step takes it alone; and that trajectory is checked
+against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1804_06205_amd import dpd, serve
+from paper_1804_06205_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dpd.lib()
+
+
+def _req(rid, L, nbeads, steps):
+    return W.Request(rid, 0.0, L, nbeads, steps, 1000 + rid)
+
+
+def _alone(w, steps):
+    with dpd.System.from_workload(w) as g:
+        g.step(steps)
+        return g.get_state()
+
+
+def _run_batch(ws, steps, admit_after, window, variant, budget=1 << 34):
+    """Admits replica r once `admit_after[r]` windows have run; returns final states."""
+    systems = [dpd.System.from_workload(w) for w in ws]
+    out = {}
+    with dpd.Batch(budget, 16, variant=variant) as b:
+        slot_of = {}
+        nwin = 0
+        while len(out) < len(ws):
+            for r, g in enumerate(systems):
+                if r not in slot_of.values() and r not in out and admit_after[r] <= nwin:
+                    slot_of[b.admit(g, steps[r])] = r
+            b.advance(window)
+            nwin += 1
+            for slot in b.poll():
+                r = slot_of.pop(slot)
+                b.retire(slot)
+                out[r] = systems[r].get_state()
+            assert nwin < 1000
+        info = b.info()
+    for g in systems:
+        g.close()
+    return [out[r] for r in range(len(ws))], info
+
+
+@pytest.mark.parametrize("variant,window", [(4, 7), (3, 16), (0, 64)])
+def test_replica_alone_equals_in_mix_bitwise(variant, window):
+    reqs = [_req(0, 6, 10, 25), _req(1, 8, 40, 40), _req(2, 7, 20, 13), _req(3, 6, 12, 1)]
+    ws = [W.replica(r) for r in reqs]
+    steps = [r.steps for r in reqs]
+    print(f"variant {variant} window {window} sizes {[w.n for w in ws]}", flush=True)
+    got, info = _run_batch(ws, steps, admit_after=[0, 0, 1, 2], window=window, variant=variant)
+    for w, st, (x, v, f, t) in zip(ws, steps, got):
+        x0, v0, f0, t0 = _alone(w, st)
+        assert t == t0 == st
+        np.testing.assert_array_equal(x, x0)
+        np.testing.assert_array_equal(v, v0)
+        np.testing.assert_array_equal(f, f0)
+    assert info["windows"] >= 1
+
+
+def test_batched_replica_follows_oracle():
+    w = W.replica(_req(7, 7, 30, 10))
+    states, _ = _run_batch([w], [10], [0], window=4, variant=4)
+    x, v, f, t = states[0]
+    st = oracle.State.from_workload(w)
+    st.step(10)
+    d = x - st.pos
+    d -= np.asarray(w.L) * np.rint(d / np.asarray(w.L))
+    err = np.abs(d).max()
+    print(f"10-step position max-abs vs oracle {err:.3e}", flush=True)
+    assert t == 10
+    assert err <= 1e-3
+
+
+def test_footprint_matches_allocation():
+    w = W.replica(_req(8, 9, 25, 5))
+    fp = dpd.footprint_bytes(w.L, w.n, w.nbonds, "mixed")
+    with dpd.System.from_workload(w) as g:
+        g.step(1)
+        assert g.info()["device_bytes"] == fp
+    w0 = W.fluid(6.0, seed=3)
+    with dpd.System.from_workload(w0) as g:
+        assert g.info()["device_bytes"] == dpd.footprint_bytes(w0.L, w0.n, 0, "mixed")
+
+
+def test_batch_admission_and_errors():
+    wa = W.replica(_req(10, 6, 10, 20))
+    wb = W.replica(_req(11, 7, 10, 20))
+    fa = dpd.footprint_bytes(wa.L, wa.n, wa.nbonds, "mixed")
+    fb = dpd.footprint_bytes(wb.L, wb.n, wb.nbonds, "mixed")
+    ga = dpd.System.from_workload(wa)
+    gb = dpd.System.from_workload(wb)
+    with dpd.Batch(max(fa, fb) + 1024, 4) as b:
+        sa = b.admit(ga, 20)
+        with pytest.raises(dpd.DPDError) as e:
+            b.admit(gb, 20)                  # over the budget
+        assert e.value.code == dpd.EBUSY
+        with pytest.raises(dpd.DPDError) as e:
+            ga.step(1)                       # resident: the batch owns it
+        assert e.value.code == dpd.EBUSY
+        with pytest.raises(dpd.DPDError) as e:
+            ga.sync()
+        assert e.value.code == dpd.EBUSY
+        with pytest.raises(dpd.DPDError) as e:
+            b.retire(3)
+        assert e.value.code == dpd.EINVAL
+        b.advance(8)
+        assert b.poll() == []
+        b.retire(sa)                         # preempted after 8 of 20 steps
+        assert ga.get_state()[3] == 8
+        ga.step(2)                           # usable again on its own
+        assert ga.get_state()[3] == 10
+        sb = b.admit(gb, 3)                  # the freed budget admits the other
+        b.advance(8)
+        assert b.poll() == [sb]
+        b.retire(sb)
+        assert gb.get_state()[3] == 3
+    ga.close()
+    gb.close()
+    # fp64 systems and non-cubic cells are refused.
+    w64 = W.fluid(6.0, seed=4, precision="fp64")
+    with dpd.System.from_workload(w64) as g, dpd.Batch(1 << 30, 2) as b:
+        with pytest.raises(dpd.DPDError) as e:
+            b.admit(g, 5)
+        assert e.value.code == dpd.EINVAL
+    rng = np.random.default_rng(9)
+    L = np.array([6.0, 7.5, 6.0])
+    n = int(3 * L.prod())
+    with dpd.System(L, rng.uniform(0, 1, (n, 3)) * L, rng.normal(size=(n, 3))) as g, \
+            dpd.Batch(1 << 30, 2) as b:
+        g.set_params([[25.0]], 4.5, 3.0, 1.0, 0.04)
+        with pytest.raises(dpd.DPDError) as e:
+            b.admit(g, 5)
+        assert e.value.code == dpd.EINVAL
+
+
+def test_destroy_while_resident_detaches():
+    w = W.replica(_req(12, 6, 10, 50))
+    with dpd.Batch(1 << 30, 2) as b:
+        g = dpd.System.from_workload(w)
+        slot = b.admit(g, 50)
+        b.advance(5)
+        b._members.pop(slot)
+        g.close()                            # retires it from the batch first
+        assert b.info()["resident"] == 0
+        b.advance(5)                         # nothing left to step
+        assert b.poll() == []
+
+
+def test_graph_is_reused_across_windows():
+    reqs = [_req(20 + k, 6 + k % 3, 10, 200) for k in range(5)]
+    ws = [W.replica(r) for r in reqs]
+    _, info = _run_batch(ws, [200] * 5, [0] * 5, window=20, variant=4)
+    print(f"windows {info['windows']} captures {info['captures']}", flush=True)
+    assert info["windows"] == 10
+    assert info["captures"] == 1
+
+
+def test_serve_small_stream_with_tight_budget():
+    reqs = W.replica_stream(nreq=12, rate=2000.0, seed=7, L_range=(6, 8), beads_range=(10, 20),
+                            steps_range=(50, 200))
+    fps = [dpd.footprint_bytes(W.replica(r).L, W.replica(r).n, W.replica(r).nbonds, "mixed")
+           for r in reqs]
+    budget = int(max(fps) * 2.5)             # at most two or three resident at once
+    recs, summ = serve.serve_batched(reqs, budget, window=32)
+    print(summ, flush=True)
+    assert len(recs) == 12 and all(np.isfinite(r.done) for r in recs)
+    assert all(r.done >= r.admitted >= r.arrival - 1e-9 for r in recs)
+    assert summ["graph_captures"] < summ["windows"]
+    recs1, summ1 = serve.serve_one_at_a_time(reqs[:3])
+    assert len(recs1) == 3 and summ1["particle_steps"] > 0
