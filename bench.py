@@ -39,7 +39,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="fluid_L96",
-                    choices=["fluid_L96", "fluid_L10", "melt_L32", "peptide_L40"])
+                    choices=["fluid_L96", "fluid_L10", "melt_L32", "peptide_L40",
+                             "replica_stream"])
+    ap.add_argument("--window", type=int, default=100,
+                    help="replica_stream: steps per batch window")
+    ap.add_argument("--budget-gib", type=float, default=64.0,
+                    help="replica_stream: device memory budget of the batch")
+    ap.add_argument("--requests", type=int, default=512,
+                    help="replica_stream: requests replayed")
+    ap.add_argument("--no-serial", action="store_true",
+                    help="replica_stream: skip the one-at-a-time baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=None,
@@ -74,6 +83,46 @@ def cpu_baseline(w, budget_s):
                       f"initial force, FP64, {threads} OpenMP threads, {el:.1f} s"}
 
 
+def replica_stream(args):
+    """Continuous batching of the replica request stream (Poisson arrivals at
+    200/s, L in 6..12, one 10-40 bead chain each, 1000-10000 steps), against
+    the same trace served one replica at a time."""
+    from paper_1804_06205_amd import serve
+    from paper_1804_06205_amd import workloads as W
+
+    reqs = W.replica_stream()[: args.requests]
+    budget = int(args.budget_gib * (1 << 30))
+    # Warm-up: the kernels' first launches and graph instantiation.
+    serve.serve_batched(W.replica_stream(nreq=4, steps_range=(50, 100)), budget,
+                        window=args.window, realtime=False)
+    _, summ = serve.serve_batched(reqs, budget, window=args.window)
+    line = {
+        "metric": "particle-steps/s (batched replicas, rho=3)",
+        "value": summ["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": int(sum(r.steps for r in reqs)),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "replica_stream", "requests": len(reqs), "arrival_rate": 200.0,
+                   "L": [6, 12], "chain_beads": [10, 40], "steps": [1000, 10000],
+                   "precision": "FP32 forces/velocities, FP64 positions",
+                   "window": args.window, "budget_bytes": budget},
+        "serving": summ,
+        "roofline": None,
+    }
+    if not args.no_serial:
+        _, s1 = serve.serve_one_at_a_time(reqs)
+        line["one_at_a_time"] = s1
+        line["speedup_vs_one_at_a_time"] = summ["particle_steps_per_s"] / s1["particle_steps_per_s"]
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -85,6 +134,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "replica_stream":
+        replica_stream(args)
+        return
     w = make_workload(args.workload)
     stream = torch.cuda.Stream()
     g = dpd.System.from_workload(w, stream=stream)

@@ -154,7 +154,9 @@ int dpd_set_params(dpd_system *sys, const double *a_ij, double gamma, double sig
 int dpd_add_bonds(dpd_system *sys, int64_t nb, const int32_t *btype, const int64_t *i,
                   const int64_t *j, const double *r_e, const double *k, const double *alpha);
 
-/* Enqueues nsteps >= 0 steps on the system's stream and returns. */
+/* Enqueues nsteps >= 0 steps on the system's stream and returns.  Any call,
+ * nsteps = 0 included, freezes the parameters and bonds and enqueues the
+ * initial force if it is not yet computed. */
 int dpd_step(dpd_system *sys, int64_t nsteps);
 
 /* Like dpd_step, but synchronises and reports per-kernel device time. */
@@ -235,7 +237,7 @@ int dpd_footprint_bytes(const double L[3], int64_t n, int64_t nbonds, int precis
  *       budget_bytes  cap on the summed device bytes (dpd_info out[3]) of the
  *                     resident systems; max_replicas  number of slots (1..65536);
  *       hip_stream    stream for the batch's work (NULL = library-owned);
- *       variant       brick variant of the batched pair pass (-1 = 2x2x2).
+ *       variant       brick variant of the batched pair pass (-1 = 5x4x4).
  *   dpd_batch_admit(b, sys, nsteps, &slot)
  *       makes sys resident with a target of nsteps more steps.  Computes the
  *       initial force if needed and waits for the system's stream and the

@@ -42,7 +42,8 @@ template <typename T> size_t prec_size() { return sizeof(T); }
 
 // Device bytes dpd_create allocates for a system (and dpd_add_bonds adds at
 // the first step), in the order of the allocations below.
-int64_t footprint(int prec, int64_t ncells, int64_t n, int64_t nb, int cap) {
+int64_t footprint(int prec, const int nc[3], int64_t n, int64_t nb, int cap) {
+    const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
     const int64_t psz = prec == DPD_PREC_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>);
     const int64_t ssz = prec == DPD_PREC_FP64 ? sizeof(SRec<double>) : sizeof(SRec<float>);
     const int64_t slots = ncells * cap;
@@ -170,6 +171,7 @@ void free_all(dpd_system *s) {
                     s->obs_ptrs, s->red};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+
 }
 
 // Reads the device error word; converts it to a sticky status.
@@ -404,6 +406,7 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
     if (!rc) rc = dmalloc(s, (void **)&s->obs_ptrs, 8 * sizeof(double *));
     s->red_blocks = (int)std::min<int64_t>(256, (n + 1023) / 1024);
     if (!rc) rc = dmalloc(s, (void **)&s->red, (size_t)s->red_blocks * 8 * sizeof(double));
+
     if (rc) {
         free_all(s);
         if (s->own_stream) (void)hipStreamDestroy(s->stream);
@@ -502,9 +505,9 @@ int dpd_add_bonds(dpd_system *s, int64_t nb, const int32_t *btype, const int64_t
 static int step_impl(dpd_system *s, int64_t nsteps, dpd_kernel_times *tm) {
     if (int rc = check_usable(s)) return rc;
     if (nsteps < 0) return fail(DPD_EINVAL, "negative step count");
-    if (nsteps == 0) return DPD_OK;
     if (int rc = freeze(s)) return rc;
     if (int rc = ensure_force(s)) return rc;
+    if (nsteps == 0) return DPD_OK;
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (tm) {
         std::memset(tm, 0, sizeof *tm);
@@ -893,7 +896,7 @@ int batch_upload(dpd_batch *b) {
     for (int k = 0; k < b->max_slots; ++k) {
         dpd_system *s = b->sys[k];
         if (!s || b->t0[k] >= b->target[k]) continue;
-        const int nbr = b->tab_h[k].nbx * b->tab_h[k].nby * ((s->nc[2] + b->bz - 1) / b->bz);
+        const int nbr = b->tab_h[k].nbx * b->tab_h[k].nby * b->tab_h[k].nbz;
         for (int i = 0; i < nbr; ++i) b->wf_v.push_back(BatchWork{(uint32_t)k, (uint32_t)i});
         const int nblk = (int)((s->ncells + 255) / 256);
         for (int i = 0; i < nblk; ++i) b->wb_v.push_back(BatchWork{(uint32_t)k, (uint32_t)i});
@@ -1000,10 +1003,10 @@ int dpd_footprint_bytes(const double L[3], int64_t n, int64_t nbonds, int precis
         return fail(DPD_EINVAL, "unknown precision %d", precision);
     if (cell_capacity < 0 || cell_capacity > 1024)
         return fail(DPD_EINVAL, "cell_capacity must be in 0..1024");
-    int64_t nc = 1;
+    int nc[3];
     for (int k = 0; k < 3; ++k) {
         if (!std::isfinite(L[k]) || L[k] < 3.0) return fail(DPD_EBOX, "box edge below 3");
-        nc *= (int64_t)std::floor(L[k]);
+        nc[k] = (int)std::floor(L[k]);
     }
     *bytes = footprint(precision, nc, n, nbonds, cell_capacity ? cell_capacity : 32);
     return DPD_OK;
@@ -1023,7 +1026,7 @@ int dpd_batch_create(dpd_batch **out, int64_t budget_bytes, int max_replicas, vo
     if (!b) return fail(DPD_ENOMEM, "host allocation failed");
     b->budget = budget_bytes;
     b->max_slots = max_replicas;
-    b->variant = variant < 0 ? 4 : variant;
+    b->variant = variant < 0 ? 1 : variant;
     int shape[5];
     force_variant_shape(b->variant, shape);
     b->bx = shape[0];
@@ -1093,6 +1096,7 @@ int dpd_batch_admit(dpd_batch *b, dpd_system *s, int64_t nsteps, int *slot) {
     e.D = make_dev<float>(s);
     e.nbx = (s->nc[0] + b->bx - 1) / b->bx;
     e.nby = (s->nc[1] + b->by - 1) / b->by;
+    e.nbz = (s->nc[2] + b->bz - 1) / b->bz;
     const double lim = 536870912.0 / s->h[0];
     e.thr = (uint64_t)std::ceil(lim * lim);
     b->tab_h[k] = e;

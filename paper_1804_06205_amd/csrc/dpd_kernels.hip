@@ -31,12 +31,12 @@ namespace dpd {
 
 constexpr int QCAP = 8;          // per-lane pending-pair queue depth (>= 5)
 constexpr int MAXTYPES = 16;
+constexpr int MAXCHUNK = 32;     // neighbourhood chunks per brick
 
 enum : int { MODE_INIT = 0, MODE_FINISH = 1, MODE_FUSED = 2, MODE_OBS = 3 };
 
-// Neighbour data staged in LDS.
+// Neighbour positions and tags staged in LDS.
 template <typename T> struct alignas(16) LA { typename Geo<T>::P ox, oy, oz; uint32_t tag; };
-template <typename T> struct alignas(16) LB { T vx, vy, vz; uint32_t type; };
 
 __device__ __forceinline__ int wrapi(int c, int n) {
     c = c < 0 ? c + n : c;
@@ -184,18 +184,35 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
 // ---------------------------------------------------------------------------
 struct alignas(16) LAI { uint32_t qx, qy, qz, tag; };
 
-// Copies halo cells [c0, c1) into LDS at their offsets relative to cell c0,
-// one thread per cell, then sorts every cell's records by tag in place.
-template <typename T, int HX, int HY, int NHC, int NT, bool IGEO, typename AT>
-__device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, const int *s_hcell,
-                                            const int *s_hstart, int c0, int c1, AT *s_A,
-                                            LB<T> *s_B) {
+// Global cell of halo cell hc of the brick with origin (c0x, c0y, c0z).
+template <int HX, int HY>
+__device__ __forceinline__ int64_t halo_cell(int hc, int c0x, int c0y, int c0z, const int nc[3]) {
+    const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+    return cell_linear(wrapi(c0x + hx - 1, nc[0]), wrapi(c0y + hy - 1, nc[1]),
+                       wrapi(c0z + hz - 1, nc[2]), nc);
+}
+
+// Neighbour data staged in LDS for one brick: positions and tags (AT), the
+// predicted velocity as three arrays and the type as bytes.
+template <typename T, typename AT, int HCAP> struct Tile {
+    AT *A;
+    T *vx, *vy, *vz;
+    uint8_t *type;
+};
+
+// Copies halo cells [c0, c1) into the tile at their offsets relative to cell
+// c0, one thread per cell, each record straight to its place in ascending tag
+// order: its rank among the cell's tags (distinct).
+template <typename T, int HX, int HY, int NT, bool IGEO, typename AT, int HCAP>
+__device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, int c0x, int c0y,
+                                            int c0z, const int *s_hstart, int c0, int c1,
+                                            const Tile<T, AT, HCAP> &tl) {
     const int cap = D.cap;
     const int off0 = s_hstart[c0];
     for (int hc = c0 + (int)threadIdx.x; hc < c1; hc += NT) {
         const int lo = s_hstart[hc] - off0, n = s_hstart[hc + 1] - s_hstart[hc];
         if (n == 0) continue;
-        const PRec<T> *src = D.P[lay] + (int64_t)s_hcell[hc] * cap;
+        const PRec<T> *src = D.P[lay] + halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc) * cap;
         const uint32_t hx = (uint32_t)(hc % HX), hy = (uint32_t)((hc / HX) % HY),
                        hz = (uint32_t)(hc / (HX * HY));
         for (int k0 = 0; k0 < n; k0 += 4) {
@@ -203,6 +220,20 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, co
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (k0 + u < n) r[u] = src[k0 + u];
+            int rank[4] = {0, 0, 0, 0};
+            if (n <= 4) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        rank[u] += (k < n && r[k].tag < r[u].tag) ? 1 : 0;
+            } else {
+                for (int k = 0; k < n; ++k) {
+                    const uint32_t tk = src[k].tag;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) rank[u] += tk < r[u].tag ? 1 : 0;
+                }
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (k0 + u < n) {
@@ -217,37 +248,26 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, co
                         a.oz = r[u].oz;
                     }
                     a.tag = r[u].tag;
-                    LB<T> bb;
-                    bb.vx = r[u].vx;
-                    bb.vy = r[u].vy;
-                    bb.vz = r[u].vz;
-                    bb.type = r[u].type;
-                    s_A[lo + k0 + u] = a;
-                    s_B[lo + k0 + u] = bb;
+                    const int j = lo + rank[u];
+                    tl.A[j] = a;
+                    tl.vx[j] = r[u].vx;
+                    tl.vy[j] = r[u].vy;
+                    tl.vz[j] = r[u].vz;
+                    tl.type[j] = (uint8_t)r[u].type;
                 }
             }
-        }
-        for (int i = lo + 1; i < lo + n; ++i) {
-            const AT a = s_A[i];
-            const LB<T> bb = s_B[i];
-            int j = i - 1;
-            while (j >= lo && s_A[j].tag > a.tag) {
-                s_A[j + 1] = s_A[j];
-                s_B[j + 1] = s_B[j];
-                --j;
-            }
-            s_A[j + 1] = a;
-            s_B[j + 1] = bb;
         }
     }
 }
 
-// Forces of state q for brick b (of nbx x nby x .. bricks).  fin (MODE_FUSED
-// only) ends the step in place like MODE_FINISH instead of moving on to state
-// q + 1; replicas of a batch use it for their last step of a window.
+// Forces of state q for brick b of an nbx x nby x nbz split of the box.  Each
+// axis of n cells is cut into m near-equal runs (cell (k n) / m starts run k),
+// each at most the compile-time extent, so no brick is a thin remainder.  fin
+// (MODE_FUSED only) ends the step in place like MODE_FINISH instead of moving
+// on to state q + 1; replicas of a batch use it for their last step of a window.
 template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO>
 __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int b, int nbx,
-                                            int nby, uint64_t thr, bool fin) {
+                                            int nby, int nbz, uint64_t thr, bool fin) {
     constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
     constexpr int NHC = HX * HY * HZ;
     constexpr int NOC = BX * BY * BZ;
@@ -260,15 +280,16 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     static_assert(!IGEO || HMAX <= 7, "brick too large for the u32 brick frame");
     using AT = typename std::conditional<IGEO, LAI, LA<T>>::type;
 
-    __shared__ int s_hcell[NHC];
     __shared__ int s_hstart[NHC + 1];
     __shared__ int s_ostart[NOC + 1];
-    __shared__ int s_chunk[NHC + 1];
+    __shared__ int s_chunk[MAXCHUNK + 1];
     __shared__ int s_wave[NT / 64];
     __shared__ int s_flag, s_nchunk;
     __shared__ T s_a[MAXTYPES * MAXTYPES];
     __shared__ AT s_A[HCAP + 4];     // + room for the 4-wide reads past a row's end
-    __shared__ LB<T> s_B[HCAP];
+    __shared__ T s_vx[HCAP], s_vy[HCAP], s_vz[HCAP];
+    __shared__ uint8_t s_t[HCAP];
+    const Tile<T, AT, HCAP> tile{s_A, s_vx, s_vy, s_vz, s_t};
     // Per-lane queues of pending neighbours: LDS indices (u16) in the integer
     // frame; index plus whole-cell shift code (u32) otherwise.
     using QT = typename std::conditional<IGEO, uint16_t, uint32_t>::type;
@@ -284,25 +305,21 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     if (s_flag) return;
 
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int c0x = bx * BX, c0y = by * BY, c0z = bz * BZ;
-    const int ex = min(BX, D.nc[0] - c0x), ey = min(BY, D.nc[1] - c0y), ez = min(BZ, D.nc[2] - c0z);
+    const int c0x = bx * D.nc[0] / nbx, c0y = by * D.nc[1] / nby, c0z = bz * D.nc[2] / nbz;
+    const int ex = (bx + 1) * D.nc[0] / nbx - c0x, ey = (by + 1) * D.nc[1] / nby - c0y,
+              ez = (bz + 1) * D.nc[2] / nbz - c0z;
 
     // Halo cells (own cells plus one layer, periodic) and their counts.
     for (int hc = tid; hc < NHC; hc += NT) {
         const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
-        int g = -1, c = 0;
+        int c = 0;
         if (hx <= ex + 1 && hy <= ey + 1 && hz <= ez + 1) {
-            const int gx = wrapi(c0x + hx - 1, D.nc[0]);
-            const int gy = wrapi(c0y + hy - 1, D.nc[1]);
-            const int gz = wrapi(c0z + hz - 1, D.nc[2]);
-            g = (int)cell_linear(gx, gy, gz, D.nc);
-            c = (int)cnt[g];
+            c = (int)cnt[halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc)];
             if (c > cap) {
                 atomicOr(D.err, ERR_INDEX);
                 c = cap;
             }
         }
-        s_hcell[hc] = g;
         s_hstart[hc] = c;
     }
     for (int i = tid; i < D.ntypes * D.ntypes; i += NT) s_a[i] = D.a[i];
@@ -327,22 +344,36 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         s_ostart[oc] = c;
     }
     // Chunks of whole halo cells that fit the LDS tile, in cell order (one
-    // chunk unless the neighbourhood is unusually dense).
+    // chunk unless the neighbourhood is unusually dense).  A single cell over
+    // the tile, or more than MAXCHUNK chunks, is a tile overflow.
     if (tid == 0) {
         int k = 0;
+        bool over = false;
         s_chunk[0] = 0;
         if (s_hstart[NHC] > HCAP) {
             int base = 0;
-            for (int hc = 0; hc < NHC; ++hc)
+            for (int hc = 0; hc < NHC; ++hc) {
+                if (s_hstart[hc + 1] - s_hstart[hc] > HCAP) {
+                    over = true;            // one cell larger than the tile
+                    break;
+                }
                 if (s_hstart[hc + 1] - base > HCAP) {
-                    s_chunk[++k] = hc;
+                    if (k + 1 >= MAXCHUNK) {
+                        over = true;
+                        break;
+                    }
+                    s_chunk[++k] = hc;      // cell hc starts a new chunk
                     base = s_hstart[hc];
                 }
+            }
         }
         s_chunk[++k] = NHC;
         s_nchunk = k;
+        s_flag = over ? 1 : 0;
+        if (over) atomicOr(D.err, ERR_TILE_OVERFLOW);
     }
     __syncthreads();
+    if (s_flag) return;
     block_scan<NT, IPT_O>(s_ostart, NOC, s_wave);
     const int nown = s_ostart[NOC];
     const int nchunk = s_nchunk;
@@ -373,15 +404,15 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             oxc = oc % BX;
             oyc = (oc / BX) % BY;
             ozc = oc / (BX * BY);
-            const int hc = ((ozc + 1) * HY + (oyc + 1)) * HX + (oxc + 1);
-            slot = (int64_t)s_hcell[hc] * cap + (qi - s_ostart[oc]);
+            slot = cell_linear(c0x + oxc, c0y + oyc, c0z + ozc, D.nc) * cap +
+                   (qi - s_ostart[oc]);
             pi = D.P[lay][slot];
         }
         if (base == 0 && nchunk == 1) {
             // Stage the whole neighbourhood once; the own-particle load above
             // is already in flight.
-            stage_cells<T, HX, HY, NHC, NT, IGEO, AT>(D, lay, s_hcell, s_hstart, 0, NHC, s_A,
-                                                     s_B);
+            stage_cells<T, HX, HY, NT, IGEO, AT, HCAP>(D, lay, c0x, c0y, c0z, s_hstart, 0, NHC,
+                                                      tile);
             __syncthreads();
         }
         // Brick-frame coordinates of i (IGEO).
@@ -408,7 +439,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                 ++qh;
                 const int j = (int)(e & 0xFFFFu);
                 const AT a = s_A[j];
-                const LB<T> bj = s_B[j];
+                const T bvx = s_vx[j], bvy = s_vy[j], bvz = s_vz[j];
+                const uint32_t btype = s_t[j];
                 T dx, dy, dz;
                 if constexpr (IGEO) {
                     if (MODE != MODE_OBS) {
@@ -422,11 +454,11 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         const T rinvu = t_rsqrt(u2);
                         const T r = u2 * rinvu * hxT;
                         const T w = (T)1 - r;
-                        const T edv = t_fma(ux, pi.vx - bj.vx,
-                                            t_fma(uy, pi.vy - bj.vy, uz * (pi.vz - bj.vz))) *
+                        const T edv = t_fma(ux, pi.vx - bvx,
+                                            t_fma(uy, pi.vy - bvy, uz * (pi.vz - bvz))) *
                                       rinvu;
                         const T th = pair_theta<T>(D.seed, pi.tag, a.tag, q);
-                        const T aij = arow[bj.type];
+                        const T aij = arow[btype];
                         const T c = t_fma(srdt * w, th, w * t_fma(-gamma * w, edv, aij)) * rinvu;
                         fx = t_fma(c, ux, fx);
                         fy = t_fma(c, uy, fy);
@@ -445,7 +477,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                     dz = Geo<T>::delta(pi.oz, a.oz, sz, hzT);
                 }
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const T aij = arow[bj.type];
+                const T aij = arow[btype];
                 if (MODE == MODE_OBS) {
                     ++onp;
                     if (r2 > (T)0) {
@@ -458,8 +490,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                     const T rinv = t_rsqrt(r2);
                     const T r = r2 * rinv;
                     const T w = (T)1 - r;
-                    const T edv = (dx * (pi.vx - bj.vx) + dy * (pi.vy - bj.vy) +
-                                   dz * (pi.vz - bj.vz)) * rinv;
+                    const T edv = (dx * (pi.vx - bvx) + dy * (pi.vy - bvy) +
+                                   dz * (pi.vz - bvz)) * rinv;
                     const T th = pair_theta<T>(D.seed, pi.tag, a.tag, q);
                     const T c = (aij * w - gamma * w * w * edv + srdt * w * th) * rinv;
                     fx += c * dx;
@@ -474,8 +506,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             const int off0 = s_hstart[clo];
             if (nchunk > 1) {
                 __syncthreads();
-                stage_cells<T, HX, HY, NHC, NT, IGEO, AT>(D, lay, s_hcell, s_hstart, clo, chi,
-                                                         s_A, s_B);
+                stage_cells<T, HX, HY, NT, IGEO, AT, HCAP>(D, lay, c0x, c0y, c0z, s_hstart, clo,
+                                                          chi, tile);
                 __syncthreads();
             }
             // Candidate scan: rows of three consecutive halo cells (clipped to
@@ -632,11 +664,16 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     }
 }
 
+// Waves per SIMD the integer-frame pair kernels are register-budgeted for.
+#ifndef DPD_WAVES_PER_EU
+#define DPD_WAVES_PER_EU 4
+#endif
+
 template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO>
-__global__ __launch_bounds__(NT) void k_force(DevSys<T> D, uint32_t q, int nbx, int nby,
-                                              int nbricks, uint64_t thr) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(IGEO ? DPD_WAVES_PER_EU : 1)))
+void k_force(DevSys<T> D, uint32_t q, int nbx, int nby, int nbricks, uint64_t thr) {
     force_brick<T, BX, BY, BZ, NT, HCAP, MODE, IGEO>(D, q, xcd_brick(blockIdx.x, nbricks), nbx,
-                                                     nby, thr, false);
+                                                     nby, nbricks / (nbx * nby), thr, false);
 }
 
 // begin: integrate-1 and binning of every particle of resting state q; one
@@ -672,8 +709,8 @@ __global__ __launch_bounds__(256) void k_begin(DevSys<T> D, uint32_t q) {
 // land in scratch); it is never written during a window, which the restrict
 // qualifier tells the compiler, so its fields stay uniform scalar loads.
 template <int BX, int BY, int BZ, int NT, int HCAP>
-__global__ __launch_bounds__(NT) void k_force_batch(const BatchEnt *__restrict__ tab,
-                                                    BatchDev B, uint32_t k, uint32_t last) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DPD_WAVES_PER_EU)))
+void k_force_batch(const BatchEnt *__restrict__ tab, BatchDev B, uint32_t k, uint32_t last) {
     const int nw = B.nwork[0];
     if ((int)blockIdx.x >= nw) return;
     const BatchWork w = B.wf[xcd_brick(blockIdx.x, nw)];
@@ -682,7 +719,8 @@ __global__ __launch_bounds__(NT) void k_force_batch(const BatchEnt *__restrict__
     const uint32_t q = t0 + k + 1u;
     const BatchEnt &E = tab[w.slot];
     force_brick<float, BX, BY, BZ, NT, HCAP, MODE_FUSED, true>(E.D, q, (int)w.item, E.nbx, E.nby,
-                                                               E.thr, q == tgt || last != 0u);
+                                                               E.nbz, E.thr,
+                                                               q == tgt || last != 0u);
 }
 
 __global__ __launch_bounds__(256) void k_begin_batch(const BatchEnt *__restrict__ tab,
@@ -892,7 +930,7 @@ static hipError_t launch_force_v(const DevSys<T> &D, uint32_t q, int mode, hipSt
 // denser neighbourhoods are processed in chunks.
 #define DPD_VARIANTS(X)                                                                   \
     X(0, 4, 4, 4, 256, 800)                                                               \
-    X(1, 5, 4, 4, 256, 900)                                                               \
+    X(1, 5, 4, 4, 256, 896)                                                               \
     X(2, 5, 5, 4, 320, 1056)                                                              \
     X(3, 4, 4, 2, 128, 540)                                                               \
     X(4, 2, 2, 2, 64, 256)

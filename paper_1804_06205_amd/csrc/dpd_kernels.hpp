@@ -35,7 +35,7 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t m, uint32_t v, hipStream_t st);
 // ---------------------------------------------------------------------------
 struct BatchEnt {
     DevSys<float> D;
-    int nbx, nby;       // bricks per axis in the batch's brick shape
+    int nbx, nby, nbz;  // bricks per axis (each at most the batch's brick extent)
     uint64_t thr;       // cutoff r^2 < 1 in squared brick-frame units
 };
 

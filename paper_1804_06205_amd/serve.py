@@ -67,10 +67,22 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
     slot_of = {}                # slot -> (record, system, footprint)
     records = []
     used = 0                    # bytes of prepared + resident systems
+    host = {"prepare": 0.0, "admit": 0.0, "advance": 0.0, "poll": 0.0, "retire": 0.0}
     t0 = time.perf_counter()
 
     def now():
         return time.perf_counter() - t0
+
+    class _clock:
+        # Host seconds spent per phase of the loop.
+        def __init__(self, key):
+            self.key = key
+
+        def __enter__(self):
+            self.t = time.perf_counter()
+
+        def __exit__(self, *exc):
+            host[self.key] += time.perf_counter() - self.t
 
     def prepare():
         # Create systems for the arrived head of the queue while they fit.
@@ -87,32 +99,39 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
             rec = Record(req.rid, 0.0 if not realtime else req.arrival, w.n, req.steps)
             records.append(rec)
             sysm = dpd.System.from_workload(w, cell_capacity=cell_capacity)
+            sysm.step(0)            # initial force, on the system's own stream
             used += fp
             prepared.append((rec, sysm, fp))
 
     try:
         while queue or prepared or slot_of:
-            prepare()
-            while prepared:
-                rec, sysm, fp = prepared.popleft()
-                slot = batch.admit(sysm, rec.steps)
-                rec.admitted = now()
-                slot_of[slot] = (rec, sysm, fp)
+            with _clock("prepare"):
+                prepare()
+            with _clock("admit"):
+                while prepared:
+                    rec, sysm, fp = prepared.popleft()
+                    slot = batch.admit(sysm, rec.steps)
+                    rec.admitted = now()
+                    slot_of[slot] = (rec, sysm, fp)
             if not slot_of:
                 if queue:
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
                 continue
-            batch.advance(window)
-            prepare()               # overlaps the window on the GPU
-            done = batch.poll()
+            with _clock("advance"):
+                batch.advance(window)
+            with _clock("prepare"):
+                prepare()           # overlaps the window on the GPU
+            with _clock("poll"):
+                done = batch.poll()
             t = now()
-            for slot in done:
-                rec, sysm, fp = slot_of.pop(slot)
-                batch.retire(slot)
-                rec.done = t
-                sysm.sync()         # surfaces a device error of this replica
-                sysm.close()
-                used -= fp
+            with _clock("retire"):
+                for slot in done:
+                    rec, sysm, fp = slot_of.pop(slot)
+                    batch.retire(slot)
+                    rec.done = t
+                    sysm.sync()     # surfaces a device error of this replica
+                    sysm.close()
+                    used -= fp
         info = batch.info()
     finally:
         for _, sysm, _ in list(prepared) + list(slot_of.values()):
@@ -122,7 +141,8 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
     return records, _summary(records, t_end, {"window": window, "budget_bytes": budget_bytes,
                                               "graph_captures": info["captures"],
                                               "windows": info["windows"],
-                                              "variant": info["variant"]})
+                                              "variant": info["variant"],
+                                              "host_s": host})
 
 
 def serve_one_at_a_time(requests, make=workloads.replica, cell_capacity: int = 0,
