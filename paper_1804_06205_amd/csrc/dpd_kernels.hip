@@ -427,17 +427,39 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         double ou = 0.0, ow = 0.0;
         uint32_t onp = 0;
         uint32_t qh = 0, qt = 0;
+        // Integer frame: a queue entry is a group of four consecutive
+        // candidates, base index | hit mask << 12; `cur` is the group being
+        // worked through.
+        uint32_t cur = 0;
         // Lanes with a particle; pending pairs are processed once 3/4 of them
         // have one queued.
         const int nact = __popcll(__ballot(have));
         const int rth = max(1, (3 * nact) / 4);
 
-        // Pops one queued neighbour per lane that has one and adds its force.
+        // Takes one pending neighbour per lane that has one (in candidate
+        // order) and adds its force.
         auto process = [&]() __attribute__((always_inline)) {
-            if (qt != qh) {
-                const uint32_t e = (uint32_t)myq[(qh % QCAP) * NT];
-                ++qh;
-                const int j = (int)(e & 0xFFFFu);
+            int j = -1;
+            uint32_t e = 0;
+            if constexpr (IGEO) {
+                if (cur == 0u && qt != qh) {
+                    cur = (uint32_t)myq[(qh % QCAP) * NT];
+                    ++qh;
+                }
+                if (cur != 0u) {
+                    const uint32_t m = cur >> 12;
+                    j = (int)(cur & 0xFFFu) + __builtin_ctz(m);
+                    const uint32_t m2 = m & (m - 1u);
+                    cur = m2 ? ((cur & 0xFFFu) | (m2 << 12)) : 0u;
+                }
+            } else {
+                if (qt != qh) {
+                    e = (uint32_t)myq[(qh % QCAP) * NT];
+                    ++qh;
+                    j = (int)(e & 0xFFFFu);
+                }
+            }
+            if (j >= 0) {
                 const AT a = s_A[j];
                 const T bvx = s_vx[j], bvy = s_vy[j], bvz = s_vz[j];
                 const uint32_t btype = s_t[j];
@@ -512,9 +534,9 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             }
             // Candidate scan: rows of three consecutive halo cells (clipped to
             // the chunk), four candidates per step with the LDS reads issued up
-            // front; misses are written to the free queue slot and not counted,
-            // so the step has no branches.  Before each step every queue has
-            // room for four more.
+            // front; the step writes the free queue slot whether or not it
+            // found a pair, so it has no branches.  Before each step every
+            // queue has room for what the step can add.
             for (int row = 0; row < 9; ++row) {
                 const int dyc = row % 3 - 1, dzc = row / 3 - 1;
                 int jb = 0, b1 = 0, b2 = 0, je = 0;
@@ -532,57 +554,66 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                 }
                 const int len = je - jb;
                 const uint32_t rowcode = (uint32_t)(((dyc + 1) << 2) | ((dzc + 1) << 4));
-                for (int t = 0; __ballot(t < len); t += 4) {
-                    AT a[4];
-                    const int rem = len - t;
-                    if constexpr (IGEO) {
-                        // Up to three reads past the row's end land in the next
-                        // cells or the padding; rem masks them.
+                if constexpr (IGEO) {
+                    // Up to three reads past the row's end (into later cells
+                    // or the tile's padding) are dropped from the step's hit
+                    // mask, as are all four once a lane's row is done.
+                    for (int t = 0; __ballot(t < len); t += 4) {
                         const AT *rowp = s_A + jb + t;
+                        AT a[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) a[u] = rowp[u];
-                    } else {
+                        uint32_t m = 0;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) a[u] = s_A[min(jb + t + u, max(je - 1, 0))];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int j = jb + t + u;
-                        bool hit;
-                        uint32_t code = 0;
-                        if constexpr (IGEO) {
+                        for (int u = 0; u < 4; ++u) {
                             const int32_t ddx = (int32_t)(pqx - a[u].qx);
                             const int32_t ddy = (int32_t)(pqy - a[u].qy);
                             const int32_t ddz = (int32_t)(pqz - a[u].qz);
-                            if (MODE == MODE_OBS) {
-                                const uint64_t r2 = (uint64_t)((int64_t)ddx * ddx +
-                                                               (int64_t)ddy * ddy +
-                                                               (int64_t)ddz * ddz);
-                                hit = (r2 < thr) & (a[u].tag != pi.tag) & (u < rem);
-                            } else {
-                                const uint64_t r2m1 = (uint64_t)((int64_t)ddx * ddx - 1 +
-                                                                 (int64_t)ddy * ddy +
-                                                                 (int64_t)ddz * ddz);
-                                hit = (r2m1 < thr1) & (u < rem);
-                            }
-                        } else {
-                            const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
-                            const T dx = Geo<T>::delta(pi.ox, a[u].ox, sx, hxT);
-                            const T dy = Geo<T>::delta(pi.oy, a[u].oy, dyc, hyT);
-                            const T dz = Geo<T>::delta(pi.oz, a[u].oz, dzc, hzT);
-                            hit = (dx * dx + dy * dy + dz * dz < (T)1) & (t + u < len) &
-                                  (a[u].tag != pi.tag);
-                            code = rowcode | (uint32_t)(sx + 1);
+                            // r^2 - 1 as an unsigned sum (each square < 2^62); the
+                            // -1 rides on the first multiply-add.
+                            const uint64_t r2m1 = (uint64_t)((int64_t)ddz * ddz - 1) +
+                                                  (uint64_t)((int64_t)ddy * ddy) +
+                                                  (uint64_t)((int64_t)ddx * ddx);
+                            bool hit;
+                            // The observables pass counts coincident pairs too
+                            // (r^2 = 0), excluding i by its tag.
+                            if (MODE == MODE_OBS) hit = (r2m1 + 1u < thr) & (a[u].tag != pi.tag);
+                            else hit = r2m1 < thr1;
+                            m |= (hit ? 1u : 0u) << u;
                         }
+                        m &= 0xFu >> (4 - min(max(len - t, 0), 4));
+                        myq[(qt % QCAP) * NT] = (QT)((uint32_t)(jb + t) | (m << 12));
+                        qt += m ? 1u : 0u;
+                        if (__popcll(__ballot(cur != 0u || qt != qh)) >= rth) process();
+                        while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
+                    }
+                } else {
+                // Offsets frame: one queue entry per in-range candidate, with
+                // its whole-cell shift code.
+                for (int t = 0; __ballot(t < len); t += 4) {
+                    AT a[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] = s_A[min(jb + t + u, max(je - 1, 0))];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = jb + t + u;
+                        const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
+                        const T dx = Geo<T>::delta(pi.ox, a[u].ox, sx, hxT);
+                        const T dy = Geo<T>::delta(pi.oy, a[u].oy, dyc, hyT);
+                        const T dz = Geo<T>::delta(pi.oz, a[u].oz, dzc, hzT);
+                        const bool hit = (dx * dx + dy * dy + dz * dz < (T)1) & (t + u < len) &
+                                         (a[u].tag != pi.tag);
+                        const uint32_t code = rowcode | (uint32_t)(sx + 1);
                         myq[(qt % QCAP) * NT] = (QT)((uint32_t)j | (code << 16));
                         qt += hit ? 1u : 0u;
                     }
                     if (__popcll(__ballot(qt != qh)) >= rth) process();
                     while (__ballot(qt - qh > (uint32_t)(QCAP - 4))) process();
                 }
+                }
             }
             // Queue entries index this chunk's LDS contents: drain before the next.
-            while (__ballot(qt != qh)) process();
+            while (__ballot(cur != 0u || qt != qh)) process();
         }
 
         if (!have) continue;
