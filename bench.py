@@ -31,6 +31,39 @@ HBM_PEAK_GBS = 8000.0
 # type 4 B) read once and written once.
 B_ALG_MIXED = 112.0
 B_ALG_FP64 = 160.0
+# Plain 32-bit VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s).
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic lane-op slots per particle of the gather formulation at rho = 3:
+# 81 candidates x 8 (three differences, three 32x32->64 multiply-adds, one
+# compare, one accumulate) + 12.57 in-range pairs x 86 (Philox4x32-10 40,
+# uniforms and Box-Muller 18 with log/sqrt/cos at quarter rate, geometry and
+# force 28).
+OPS_PER_PARTICLE = 81 * 8 + 12.57 * 86
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_fluid_L96_traffic.md")
+KERNEL_SOURCES = ["paper_1804_06205_amd/csrc/dpd_kernels.hip",
+                  "paper_1804_06205_amd/csrc/dpd_device.hpp",
+                  "paper_1804_06205_amd/csrc/dpd_kernels.hpp"]
+
+
+def measured_traffic(variant):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on these kernel sources and this brick."""
+    import hashlib
+    import re
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch=(\d+) variant=(\d+) sources_sha256=([0-9a-f]+)", txt)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != m.group(3) or int(m.group(2)) != variant:
+        return None
+    return float(m.group(1))
 
 
 def parse():
@@ -174,6 +207,8 @@ def main():
     fused_ms = kt["ms_fused"] / max(1, kt["n_fused"])
     b_alg = B_ALG_FP64 if w.precision == "fp64" else B_ALG_MIXED
     achieved = b_alg * w.n / (fused_ms / 1e3) / 1e9
+    alu = OPS_PER_PARTICLE * w.n / (fused_ms / 1e3)
+    traffic = measured_traffic(variant) if w.name == "fluid_L96" else None
     info = g.info()
     obs = g.observables()
     g.close()
@@ -199,9 +234,13 @@ def main():
                    "brick": list(dpd.variants()[variant][:3]),
                    "threads_per_block": dpd.variants()[variant][3]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
                      "kernel": "k_force (fused)", "kernel_ms": fused_ms,
                      "bytes_per_particle_step": b_alg},
+        "roofline_alu": {"bound": "alu", "achieved": alu / 1e12, "peak": VALU_PEAK / 1e12,
+                         "unit": "Tlane-op/s", "frac": alu / VALU_PEAK,
+                         "ops_per_particle_step": OPS_PER_PARTICLE},
         "kernel_ms": {"begin": kt["ms_begin"] / max(1, kt["n_begin"]), "fused": fused_ms,
                       "finish": kt["ms_finish"] / max(1, kt["n_finish"])},
         "final_kT": obs["kT"],
