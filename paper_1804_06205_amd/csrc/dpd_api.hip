@@ -40,22 +40,61 @@ int fail(int code, const char *fmt, ...) {
 
 template <typename T> size_t prec_size() { return sizeof(T); }
 
-// Device bytes dpd_create allocates for a system (and dpd_add_bonds adds at
-// the first step), in the order of the allocations below.
-int64_t footprint(int prec, const int nc[3], int64_t n, int64_t nb, int cap) {
-    const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
+// A system's device buffers live in one allocation (and its bond tables in a
+// second one, made at the first step), each buffer at a 256-byte boundary.
+enum Buf : int {
+    B_P0, B_P1, B_S0, B_S1, B_SOT0, B_SOT1, B_CNT0, B_CNT1, B_CNT2, B_A, B_ERR, B_STAGE,
+    B_CSTAGE, B_TYPE, B_OBS, B_OBSNP, B_OBSPTR, B_RED, B_NBUF
+};
+
+int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+int red_blocks_for(int64_t n) { return (int)std::min<int64_t>(256, (n + 1023) / 1024); }
+
+struct Layout {
+    int64_t off[B_NBUF];
+    int64_t total;
+};
+
+Layout system_layout(int prec, int64_t ncells, int64_t n, int cap) {
     const int64_t psz = prec == DPD_PREC_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>);
     const int64_t ssz = prec == DPD_PREC_FP64 ? sizeof(SRec<double>) : sizeof(SRec<float>);
     const int64_t slots = ncells * cap;
-    const int64_t red_blocks = std::min<int64_t>(256, (n + 1023) / 1024);
-    int64_t b = 2 * (slots * psz + slots * ssz + n * (int64_t)sizeof(uint32_t));
-    b += 3 * ncells * (int64_t)sizeof(uint32_t);
-    b += 256 * (int64_t)sizeof(double) + (int64_t)sizeof(uint32_t);
-    b += 9 * n * (int64_t)sizeof(double) + n * (int64_t)sizeof(int64_t) + n;
-    b += 9 * n * (int64_t)sizeof(double) + n * (int64_t)sizeof(uint32_t);
-    b += 8 * (int64_t)sizeof(double *) + red_blocks * 8 * (int64_t)sizeof(double);
-    if (nb > 0)
-        b += (n + 1) * (int64_t)sizeof(uint32_t) + 2 * nb * (int64_t)sizeof(BondEnt<double>);
+    int64_t size[B_NBUF];
+    size[B_P0] = size[B_P1] = slots * psz;
+    size[B_S0] = size[B_S1] = slots * ssz;
+    size[B_SOT0] = size[B_SOT1] = n * (int64_t)sizeof(uint32_t);
+    size[B_CNT0] = size[B_CNT1] = size[B_CNT2] = ncells * (int64_t)sizeof(uint32_t);
+    size[B_A] = 256 * (int64_t)sizeof(double);
+    size[B_ERR] = sizeof(uint32_t);
+    size[B_STAGE] = 9 * n * (int64_t)sizeof(double);      // x, v, f in tag order
+    size[B_CSTAGE] = n * (int64_t)sizeof(int64_t);
+    size[B_TYPE] = n;
+    size[B_OBS] = 9 * n * (int64_t)sizeof(double);        // per-tag observables
+    size[B_OBSNP] = n * (int64_t)sizeof(uint32_t);
+    size[B_OBSPTR] = 8 * (int64_t)sizeof(double *);
+    size[B_RED] = (int64_t)red_blocks_for(n) * 8 * (int64_t)sizeof(double);
+    Layout L;
+    int64_t o = 0;
+    for (int k = 0; k < B_NBUF; ++k) {
+        L.off[k] = o;
+        o += align256(size[k]);
+    }
+    L.total = o;
+    return L;
+}
+
+int64_t bond_block_bytes(int64_t n, int64_t nb) {
+    return align256((n + 1) * (int64_t)sizeof(uint32_t)) +
+           align256(2 * nb * (int64_t)sizeof(BondEnt<double>));
+}
+
+// Device bytes dpd_create allocates for a system, plus what dpd_add_bonds
+// adds at the first step for nb bond records.
+int64_t footprint(int prec, const int nc[3], int64_t n, int64_t nb, int cap) {
+    const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t b = system_layout(prec, ncells, n, cap).total;
+    if (nb > 0) b += bond_block_bytes(n, nb);
     return b;
 }
 
@@ -93,6 +132,8 @@ struct dpd_system {
     uint32_t *bond_off = nullptr;
     void *bonds = nullptr;
     uint32_t *err = nullptr;
+    void *block = nullptr;          // the one allocation holding the buffers below
+    void *bond_block = nullptr;     // bond CSR and records
     double *stage = nullptr;        // 9n doubles: x, v, f in tag order
     int64_t *cell_stage = nullptr;  // n
     uint8_t *type_dev = nullptr;
@@ -165,13 +206,9 @@ int dmalloc(dpd_system *s, void **p, size_t bytes) {
 }
 
 void free_all(dpd_system *s) {
-    void *ptrs[] = {s->P[0], s->P[1], s->S[0], s->S[1], s->slot_of_tag[0], s->slot_of_tag[1],
-                    s->count[0], s->count[1], s->count[2], s->a_dev, s->bond_off, s->bonds,
-                    s->err, s->stage, s->cell_stage, s->type_dev, s->obs, s->obs_np,
-                    s->obs_ptrs, s->red};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-
+    if (s->block) (void)hipFree(s->block);
+    if (s->bond_block) (void)hipFree(s->bond_block);
+    s->block = s->bond_block = nullptr;
 }
 
 // Reads the device error word; converts it to a sticky status.
@@ -227,8 +264,10 @@ template <typename T> int upload_params(dpd_system *s) {
             e.partner = (uint32_t)s->bi[b];
             ent[fill[s->bj[b]]++] = e;
         }
-        if (dmalloc(s, (void **)&s->bond_off, (n + 1) * sizeof(uint32_t))) return DPD_ENOMEM;
-        if (dmalloc(s, &s->bonds, ent.size() * sizeof(BondEnt<T>))) return DPD_ENOMEM;
+        static_assert(sizeof(BondEnt<T>) == sizeof(BondEnt<double>), "bond record size");
+        if (dmalloc(s, &s->bond_block, (size_t)bond_block_bytes(n, nb))) return DPD_ENOMEM;
+        s->bond_off = (uint32_t *)s->bond_block;
+        s->bonds = (char *)s->bond_block + align256((n + 1) * (int64_t)sizeof(uint32_t));
         HIP_OK(hipMemcpyAsync(s->bond_off, off.data(), off.size() * sizeof(uint32_t),
                               hipMemcpyHostToDevice, s->stream));
         HIP_OK(hipMemcpyAsync(s->bonds, ent.data(), ent.size() * sizeof(BondEnt<T>),
@@ -385,28 +424,31 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
         }
         s->own_stream = true;
     }
-    const size_t psz = precision == DPD_PREC_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>);
-    const size_t ssz = precision == DPD_PREC_FP64 ? sizeof(SRec<double>) : sizeof(SRec<float>);
-    const size_t slots = (size_t)s->ncells * s->cap;
-    int rc = DPD_OK;
-    for (int k = 0; k < 2 && !rc; ++k) {
-        rc = dmalloc(s, &s->P[k], slots * psz);
-        if (!rc) rc = dmalloc(s, &s->S[k], slots * ssz);
-        if (!rc) rc = dmalloc(s, (void **)&s->slot_of_tag[k], n * sizeof(uint32_t));
+    const Layout lay = system_layout(precision, s->ncells, n, s->cap);
+    int rc = dmalloc(s, &s->block, (size_t)lay.total);
+    if (!rc) {
+        char *base = (char *)s->block;
+        auto at = [&](Buf k) { return (void *)(base + lay.off[k]); };
+        s->P[0] = at(B_P0);
+        s->P[1] = at(B_P1);
+        s->S[0] = at(B_S0);
+        s->S[1] = at(B_S1);
+        s->slot_of_tag[0] = (uint32_t *)at(B_SOT0);
+        s->slot_of_tag[1] = (uint32_t *)at(B_SOT1);
+        s->count[0] = (uint32_t *)at(B_CNT0);
+        s->count[1] = (uint32_t *)at(B_CNT1);
+        s->count[2] = (uint32_t *)at(B_CNT2);
+        s->a_dev = at(B_A);
+        s->err = (uint32_t *)at(B_ERR);
+        s->stage = (double *)at(B_STAGE);
+        s->cell_stage = (int64_t *)at(B_CSTAGE);
+        s->type_dev = (uint8_t *)at(B_TYPE);
+        s->obs = (double *)at(B_OBS);
+        s->obs_np = (uint32_t *)at(B_OBSNP);
+        s->obs_ptrs = (double **)at(B_OBSPTR);
+        s->red = (double *)at(B_RED);
     }
-    for (int k = 0; k < 3 && !rc; ++k)
-        rc = dmalloc(s, (void **)&s->count[k], s->ncells * sizeof(uint32_t));
-    if (!rc) rc = dmalloc(s, &s->a_dev, 256 * sizeof(double));
-    if (!rc) rc = dmalloc(s, (void **)&s->err, sizeof(uint32_t));
-    if (!rc) rc = dmalloc(s, (void **)&s->stage, 9 * n * sizeof(double));
-    if (!rc) rc = dmalloc(s, (void **)&s->cell_stage, n * sizeof(int64_t));
-    if (!rc) rc = dmalloc(s, (void **)&s->type_dev, n);
-    if (!rc) rc = dmalloc(s, (void **)&s->obs, 9 * n * sizeof(double));
-    if (!rc) rc = dmalloc(s, (void **)&s->obs_np, n * sizeof(uint32_t));
-    if (!rc) rc = dmalloc(s, (void **)&s->obs_ptrs, 8 * sizeof(double *));
-    s->red_blocks = (int)std::min<int64_t>(256, (n + 1023) / 1024);
-    if (!rc) rc = dmalloc(s, (void **)&s->red, (size_t)s->red_blocks * 8 * sizeof(double));
-
+    s->red_blocks = red_blocks_for(n);
     if (rc) {
         free_all(s);
         if (s->own_stream) (void)hipStreamDestroy(s->stream);

@@ -103,8 +103,17 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
             used += fp
             prepared.append((rec, sysm, fp))
 
+    retired = []                # (system, footprint) retired, freed while the next window runs
+
+    def free_retired():
+        nonlocal used
+        for sysm, fp in retired:
+            sysm.close()
+            used -= fp
+        retired.clear()
+
     try:
-        while queue or prepared or slot_of:
+        while queue or prepared or slot_of or retired:
             with _clock("prepare"):
                 prepare()
             with _clock("admit"):
@@ -114,13 +123,17 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
                     rec.admitted = now()
                     slot_of[slot] = (rec, sysm, fp)
             if not slot_of:
-                if queue:
+                with _clock("retire"):
+                    free_retired()
+                if queue and not prepared:
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
                 continue
             with _clock("advance"):
                 batch.advance(window)
             with _clock("prepare"):
                 prepare()           # overlaps the window on the GPU
+            with _clock("retire"):
+                free_retired()      # also overlaps it
             with _clock("poll"):
                 done = batch.poll()
             t = now()
@@ -130,11 +143,12 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
                     batch.retire(slot)
                     rec.done = t
                     sysm.sync()     # surfaces a device error of this replica
-                    sysm.close()
-                    used -= fp
+                    retired.append((sysm, fp))
         info = batch.info()
     finally:
         for _, sysm, _ in list(prepared) + list(slot_of.values()):
+            sysm.close()
+        for sysm, _ in retired:
             sysm.close()
         batch.close()
     t_end = max(r.done for r in records)
