@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="fluid_L96",
                     choices=["fluid_L96", "fluid_L10", "melt_L32", "peptide_L40",
-                             "replica_stream"])
+                             "replica_stream", "paper_sweep"])
     ap.add_argument("--window", type=int, default=100,
                     help="replica_stream: steps per batch window")
     ap.add_argument("--budget-gib", type=float, default=64.0,
@@ -156,6 +156,109 @@ def replica_stream(args):
     print(json.dumps(line), flush=True)
 
 
+# CAMUS times from the paper's Table 1 (ms per step, 2x Xeon E5-2640, rho = 3,
+# a = 25): one thread, and the best thread count with that count.
+PAPER_TABLE1 = {5000: (10.1, 2.8, 12), 10000: (20.5, 5.1, 16), 50000: (99.0, 24.8, 12),
+                100000: (194.5, 48.7, 8)}
+
+
+def cpu_baseline_ms(w, nthreads, gomp):
+    """CPU baseline: the oracle (FP64, OpenMP) on nthreads host threads, ms per
+    step after its initial force (at least 3 steps and 1 s)."""
+    import oracle
+    gomp.omp_set_num_threads(nthreads)
+    st = oracle.State.from_workload(w)
+    st.step(1)
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < 3 or time.perf_counter() - t0 < 1.0:
+        st.step(1)
+        steps += 1
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _gpu_ms_per_step(g, steps, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    g.sync()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def paper_sweep(args):
+    """The paper's benchmark boxes (single-species fluid, rho = 3, a = 25,
+    N = 5k..100k): GPU ms/step through dpd_step and through a one-replica batch
+    (graph-captured windows), and the oracle at one and at all host threads,
+    with the paper's CAMUS times beside them.  Acc = 100 T1 / T and
+    Par = Acc / threads as in the paper's Eqs. 9-10, T1 = the oracle on one
+    thread."""
+    import ctypes
+    import torch
+    import oracle
+    from paper_1804_06205_amd import dpd
+    from paper_1804_06205_amd import workloads as W
+
+    oracle.lib()                      # loads the OpenMP runtime the oracle uses
+    gomp = ctypes.CDLL("libgomp.so.1")
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    stream = torch.cuda.Stream()
+    rows = []
+    for N in sorted(PAPER_TABLE1):
+        L = (N / 3.0) ** (1.0 / 3.0)
+        w = W.fluid(L, seed=11, name=f"fluid_N{N}")
+        g = dpd.System.from_workload(w, stream=stream)
+        g.step(args.warmup)
+        g.sync()
+        variant, _ = g.autotune(3)
+        ms = _gpu_ms_per_step(g, args.steps, stream)
+        g.close()
+        # One replica through the batch path: K-step windows replayed as a graph.
+        K = 100
+        g = dpd.System.from_workload(w)
+        with dpd.Batch(1 << 40, 1, variant=variant) as b:
+            b.admit(g, 10 ** 7)
+            b.advance(K)
+            b.poll()
+            t0 = time.perf_counter()
+            nwin = max(1, args.steps // K)
+            for _ in range(nwin):
+                b.advance(K)
+            b.poll()
+            ms_graph = (time.perf_counter() - t0) * 1e3 / (nwin * K)
+        g.close()
+        t_or = {nt: cpu_baseline_ms(w, nt, gomp) for nt in (1, nthreads)}
+        gomp.omp_set_num_threads(nthreads)
+        p1, pbest, pth = PAPER_TABLE1[N]
+        best = min(ms, ms_graph)
+        rows.append({"N": N, "L": L, "brick": list(dpd.variants()[variant][:3]),
+                     "gpu_ms_per_step": ms, "gpu_graph_ms_per_step": ms_graph,
+                     "gpu_particle_steps_per_s": N / best * 1e3,
+                     "oracle_ms_1thread": t_or[1], "oracle_ms_all": t_or[nthreads],
+                     "oracle_threads": nthreads,
+                     "acc_gpu": 100.0 * t_or[1] / best,
+                     "acc_oracle": 100.0 * t_or[1] / t_or[nthreads],
+                     "par_oracle": 100.0 * t_or[1] / t_or[nthreads] / nthreads,
+                     "paper_camus_ms_1thread": p1, "paper_camus_ms_best": pbest,
+                     "paper_camus_best_threads": pth})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    top = rows[-1]
+    line = {"metric": "particle-steps/s (paper box sizes, rho=3)",
+            "value": top["gpu_particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": min(top["gpu_ms_per_step"], top["gpu_graph_ms_per_step"]),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "paper_sweep", "N": sorted(PAPER_TABLE1), "rho": 3, "a": 25.0,
+                       "gamma": 4.5, "sigma": 3.0, "dt": 0.04,
+                       "precision": "FP32 forces/velocities, FP64 positions"},
+            "sweep": rows, "roofline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -169,6 +272,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "replica_stream":
         replica_stream(args)
+        return
+    if args.workload == "paper_sweep":
+        paper_sweep(args)
         return
     w = make_workload(args.workload)
     stream = torch.cuda.Stream()
