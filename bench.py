@@ -10,8 +10,9 @@ F^C + F^D + F^R with Philox noise, bonds (none here), integrate-2.  The timed
 region runs `--steps` consecutive steps with the state resident in HBM,
 bracketed by HIP events on the library's stream.
 
-Prints one JSON line: metric, value, roofline of the dominant kernel and the
-CPU baseline (the FP64 oracle on the host cores, on a bounded sample).
+Prints one JSON line: metric, value (median of five timed runs), roofline of
+the dominant kernel and the CPU baseline (the FP64 oracle on the host cores, on
+a bounded sample).
 """
 from __future__ import annotations
 
@@ -97,6 +98,17 @@ def make_workload(name):
             "melt_L32": W.cfg_melt_L32, "peptide_L40": W.cfg_peptide_L40}[name]()
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, budget_s):
     """The oracle (FP64, OpenMP) on the host cores, stepped until budget_s."""
     import oracle
@@ -111,7 +123,7 @@ def cpu_baseline(w, budget_s):
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": w.n * steps / el, "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(),
             "sample": f"{steps} step(s) of the same {w.name} box ({w.n} particles) after its "
                       f"initial force, FP64, {threads} OpenMP threads, {el:.1f} s"}
 
@@ -296,14 +308,20 @@ def main():
     else:
         variant = args.variant
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    g.step(args.steps)
-    e1.record(stream)
-    g.sync()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    # The timed region: `steps` consecutive steps, five times; the median run
+    # is reported (the runs continue one trajectory).
+    runs = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g.step(args.steps)
+        e1.record(stream)
+        g.sync()
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1))
+    ms = sorted(runs)[2]
     ms_step = ms / args.steps
     value = w.n * args.steps / (ms / 1e3)
 
@@ -350,6 +368,7 @@ def main():
         "kernel_ms": {"begin": kt["ms_begin"] / max(1, kt["n_begin"]), "fused": fused_ms,
                       "finish": kt["ms_finish"] / max(1, kt["n_finish"])},
         "final_kT": obs["kT"],
+        "ms_per_step_runs": [r / args.steps for r in runs],
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -32,6 +32,11 @@ namespace dpd {
 constexpr int QCAP = 8;          // per-lane pending-pair queue depth (>= 5)
 constexpr int MAXTYPES = 16;
 constexpr int MAXCHUNK = 32;     // neighbourhood chunks per brick
+// Pair rounds start once this fraction of a wave's lanes hold a pending pair.
+#ifndef DPD_ROUND_NUM
+#define DPD_ROUND_NUM 15
+#define DPD_ROUND_DEN 16
+#endif
 
 enum : int { MODE_INIT = 0, MODE_FINISH = 1, MODE_FUSED = 2, MODE_OBS = 3 };
 
@@ -423,18 +428,22 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             pqz = (uint32_t)pi.oz + ((uint32_t)(ozc + 1) << 29);
         }
         const T *arow = s_a + (int)pi.type * ntypes;
+        const T a00 = s_a[0];
         T fx = 0, fy = 0, fz = 0;
         double ou = 0.0, ow = 0.0;
         uint32_t onp = 0;
         uint32_t qh = 0, qt = 0;
         // Integer frame: a queue entry is a group of four consecutive
         // candidates, base index | hit mask << 12; `cur` is the group being
-        // worked through.
+        // worked through.  cur == 0 only while the queue is empty: a group
+        // goes straight to cur when cur is empty, and cur is refilled from
+        // the queue as soon as it runs out (the read's latency then hides
+        // behind the pair term).
         uint32_t cur = 0;
         // Lanes with a particle; pending pairs are processed once 3/4 of them
         // have one queued.
         const int nact = __popcll(__ballot(have));
-        const int rth = max(1, (3 * nact) / 4);
+        const int rth = max(1, (DPD_ROUND_NUM * nact) / DPD_ROUND_DEN);
 
         // Takes one pending neighbour per lane that has one (in candidate
         // order) and adds its force.
@@ -442,15 +451,15 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             int j = -1;
             uint32_t e = 0;
             if constexpr (IGEO) {
-                if (cur == 0u && qt != qh) {
-                    cur = (uint32_t)myq[(qh % QCAP) * NT];
-                    ++qh;
-                }
                 if (cur != 0u) {
                     const uint32_t m = cur >> 12;
                     j = (int)(cur & 0xFFFu) + __builtin_ctz(m);
                     const uint32_t m2 = m & (m - 1u);
                     cur = m2 ? ((cur & 0xFFFu) | (m2 << 12)) : 0u;
+                    if (cur == 0u && qt != qh) {
+                        cur = (uint32_t)myq[(qh % QCAP) * NT];
+                        ++qh;
+                    }
                 }
             } else {
                 if (qt != qh) {
@@ -462,7 +471,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             if (j >= 0) {
                 const AT a = s_A[j];
                 const T bvx = s_vx[j], bvy = s_vy[j], bvz = s_vz[j];
-                const uint32_t btype = s_t[j];
+
                 T dx, dy, dz;
                 if constexpr (IGEO) {
                     if (MODE != MODE_OBS) {
@@ -480,7 +489,9 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                                             t_fma(uy, pi.vy - bvy, uz * (pi.vz - bvz))) *
                                       rinvu;
                         const T th = pair_theta<T>(D.seed, pi.tag, a.tag, q);
-                        const T aij = arow[btype];
+                        // One particle type: a_ij is a constant (no per-pair
+                        // type and table reads).
+                        const T aij = ntypes == 1 ? a00 : arow[s_t[j]];
                         const T c = t_fma(srdt * w, th, w * t_fma(-gamma * w, edv, aij)) * rinvu;
                         fx = t_fma(c, ux, fx);
                         fy = t_fma(c, uy, fy);
@@ -499,7 +510,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                     dz = Geo<T>::delta(pi.oz, a.oz, sz, hzT);
                 }
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const T aij = arow[btype];
+                const T aij = arow[s_t[j]];
                 if (MODE == MODE_OBS) {
                     ++onp;
                     if (r2 > (T)0) {
@@ -582,9 +593,12 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                             m |= (hit ? 1u : 0u) << u;
                         }
                         m &= 0xFu >> (4 - min(max(len - t, 0), 4));
-                        myq[(qt % QCAP) * NT] = (QT)((uint32_t)(jb + t) | (m << 12));
-                        qt += m ? 1u : 0u;
-                        if (__popcll(__ballot(cur != 0u || qt != qh)) >= rth) process();
+                        const uint32_t entry = (uint32_t)(jb + t) | (m << 12);
+                        const bool direct = (m != 0u) & (cur == 0u);
+                        myq[(qt % QCAP) * NT] = (QT)entry;     // free slot, used or not
+                        qt += (m != 0u) & !direct ? 1u : 0u;
+                        cur = direct ? entry : cur;
+                        if (__popcll(__ballot(cur != 0u)) >= rth) process();
                         while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
                     }
                 } else {
