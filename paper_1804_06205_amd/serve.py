@@ -4,9 +4,9 @@ A stream of requests (arrival time, box, chain, step count, seed) is served by
 one replica batch (dpd_batch_*): requests are admitted in arrival order as soon
 as their device footprint fits the memory budget, every resident replica
 advances by windows of K steps (one captured HIP graph per window), and a
-finished replica is retired and freed at the end of its window.  The systems
-for newly arrived requests are created on the host while a window runs on the
-GPU.
+finished replica is retired at the end of its window and freed while the next
+one runs.  The systems for newly arrived requests (and their initial forces)
+are created while a window runs on the GPU, and admitted before the next one.
 
 `serve_one_at_a_time` replays the same stream with each replica stepped alone
 by plain dpd_step, first come first served, as the baseline.
@@ -114,8 +114,12 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
 
     try:
         while queue or prepared or slot_of or retired:
-            with _clock("prepare"):
-                prepare()
+            if not slot_of:
+                # Nothing on the GPU: create now.  Otherwise systems are
+                # created only while a window runs, never in the gap between
+                # windows.
+                with _clock("prepare"):
+                    prepare()
             with _clock("admit"):
                 while prepared:
                     rec, sysm, fp = prepared.popleft()
