@@ -596,7 +596,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         const uint32_t entry = (uint32_t)(jb + t) | (m << 12);
                         const bool direct = (m != 0u) & (cur == 0u);
                         myq[(qt % QCAP) * NT] = (QT)entry;     // free slot, used or not
-                        qt += (m != 0u) & !direct ? 1u : 0u;
+                        qt += ((m != 0u) & !direct) ? 1u : 0u;
                         cur = direct ? entry : cur;
                         if (__popcll(__ballot(cur != 0u)) >= rth) process();
                         while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
