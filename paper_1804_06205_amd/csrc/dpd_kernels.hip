@@ -55,38 +55,64 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// Exclusive prefix sum of a[0..m) in place (m <= NT * IPT), a[m] = total.
-// All threads of the block must call it.
-template <int NT, int IPT>
-__device__ void block_scan(int *a, int m, int *s_wave) {
+// Exclusive prefix sums of a[0..ma) and b[0..mb) in place, in one pass
+// (ma <= NT * IPTA, mb <= NT * IPTB); a[ma] and b[mb] get the totals.
+// s_wave holds 2 * NT / 64 ints.  All threads of the block must call it.
+template <int NT, int IPTA, int IPTB>
+__device__ void block_scan2(int *a, int ma, int *b, int mb, int *s_wave) {
+    constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    int v[IPT];
-    int sum = 0;
+    int va[IPTA], vb[IPTB];
+    int sa = 0, sb = 0;
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-        const int idx = tid * IPT + k;
-        v[k] = idx < m ? a[idx] : 0;
-        sum += v[k];
+    for (int k = 0; k < IPTA; ++k) {
+        const int idx = tid * IPTA + k;
+        va[k] = idx < ma ? a[idx] : 0;
+        sa += va[k];
     }
-    int incl = sum;
+#pragma unroll
+    for (int k = 0; k < IPTB; ++k) {
+        const int idx = tid * IPTB + k;
+        vb[k] = idx < mb ? b[idx] : 0;
+        sb += vb[k];
+    }
+    int ia = sa, ib = sb;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += t;
+        const int ta = __shfl_up(ia, off, 64), tb = __shfl_up(ib, off, 64);
+        if (lane >= off) {
+            ia += ta;
+            ib += tb;
+        }
     }
-    if (lane == 63) s_wave[wid] = incl;
+    if (lane == 63) {
+        s_wave[wid] = ia;
+        s_wave[NW + wid] = ib;
+    }
     __syncthreads();
-    int wbase = 0;
-    for (int w = 0; w < wid; ++w) wbase += s_wave[w];
-    int run = wbase + incl - sum;
-#pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-        const int idx = tid * IPT + k;
-        if (idx < m) a[idx] = run;
-        run += v[k];
+    int wa = 0, wb = 0;
+    for (int w = 0; w < wid; ++w) {
+        wa += s_wave[w];
+        wb += s_wave[NW + w];
     }
-    if (tid == NT - 1) a[m] = run;
+    int ra = wa + ia - sa, rb = wb + ib - sb;
+#pragma unroll
+    for (int k = 0; k < IPTA; ++k) {
+        const int idx = tid * IPTA + k;
+        if (idx < ma) a[idx] = ra;
+        ra += va[k];
+    }
+#pragma unroll
+    for (int k = 0; k < IPTB; ++k) {
+        const int idx = tid * IPTB + k;
+        if (idx < mb) b[idx] = rb;
+        rb += vb[k];
+    }
+    if (tid == NT - 1) {
+        a[ma] = ra;
+        b[mb] = rb;
+    }
     __syncthreads();
 }
 
@@ -288,7 +314,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     __shared__ int s_hstart[NHC + 1];
     __shared__ int s_ostart[NOC + 1];
     __shared__ int s_chunk[MAXCHUNK + 1];
-    __shared__ int s_wave[NT / 64];
+    __shared__ int s_wave[2 * (NT / 64)];
     __shared__ int s_flag, s_nchunk;
     __shared__ T s_a[MAXTYPES * MAXTYPES];
     __shared__ AT s_A[HCAP + 4];     // + room for the 4-wide reads past a row's end
@@ -305,9 +331,9 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     const uint32_t *cnt = D.count[q % 3u];
     const int cap = D.cap;
 
+    // The sticky error word is read with the halo counts (no round trip of
+    // its own); a brick of a failed system stops after that phase.
     if (tid == 0) s_flag = (int)*D.err;
-    __syncthreads();
-    if (s_flag) return;
 
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int c0x = bx * D.nc[0] / nbx, c0y = by * D.nc[1] / nby, c0z = bz * D.nc[2] / nbz;
@@ -326,6 +352,11 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             }
         }
         s_hstart[hc] = c;
+        // Own cells (halo cells 1..B along each axis; those past a short
+        // brick's extent hold no own particle).
+        if (hx >= 1 && hx <= BX && hy >= 1 && hy <= BY && hz >= 1 && hz <= BZ)
+            s_ostart[((hz - 1) * BY + (hy - 1)) * BX + (hx - 1)] =
+                (hx <= ex && hy <= ey && hz <= ez) ? c : 0;
     }
     for (int i = tid; i < D.ntypes * D.ntypes; i += NT) s_a[i] = D.a[i];
     if (MODE == MODE_FUSED) {
@@ -338,19 +369,15 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         }
     }
     __syncthreads();
-    block_scan<NT, IPT_H>(s_hstart, NHC, s_wave);
-    for (int oc = tid; oc < NOC; oc += NT) {
-        const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
-        int c = 0;
-        if (ox < ex && oy < ey && oz < ez) {
-            const int hc = ((oz + 1) * HY + (oy + 1)) * HX + (ox + 1);
-            c = s_hstart[hc + 1] - s_hstart[hc];
-        }
-        s_ostart[oc] = c;
-    }
-    // Chunks of whole halo cells that fit the LDS tile, in cell order (one
-    // chunk unless the neighbourhood is unusually dense).  A single cell over
-    // the tile, or more than MAXCHUNK chunks, is a tile overflow.
+    if (s_flag) return;
+    block_scan2<NT, IPT_H, IPT_O>(s_hstart, NHC, s_ostart, NOC, s_wave);
+    const int nown = s_ostart[NOC];
+    // Chunks of whole halo cells that fit the LDS tile, in cell order: one
+    // chunk unless the neighbourhood is unusually dense (then planned by one
+    // thread).  A single cell over the tile, or more than MAXCHUNK chunks, is
+    // a tile overflow.
+    int nchunk = 1;
+    if (s_hstart[NHC] > HCAP) {
     if (tid == 0) {
         int k = 0;
         bool over = false;
@@ -379,9 +406,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     }
     __syncthreads();
     if (s_flag) return;
-    block_scan<NT, IPT_O>(s_ostart, NOC, s_wave);
-    const int nown = s_ostart[NOC];
-    const int nchunk = s_nchunk;
+    nchunk = s_nchunk;
+    }
 
     // Per-axis scale from offset units to length.
     const T hxT = (T)Geo<T>::hscale(D.h[0]), hyT = (T)Geo<T>::hscale(D.h[1]),
@@ -535,7 +561,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         };
 
         for (int k = 0; k < nchunk; ++k) {
-            const int clo = s_chunk[k], chi = s_chunk[k + 1];
+            const int clo = nchunk == 1 ? 0 : s_chunk[k];
+            const int chi = nchunk == 1 ? NHC : s_chunk[k + 1];
             const int off0 = s_hstart[clo];
             if (nchunk > 1) {
                 __syncthreads();
