@@ -221,6 +221,47 @@ def test_full_size_fluid_binning_and_forces():
     assert err <= TOL_F["mixed"], err
 
 
+def test_full_size_fused_steps_on_the_bench_brick():
+    # The bench's launch configuration: the 5x4x4 brick, fused step passes,
+    # the full 2.65M-particle box; three steps against the oracle's.
+    w = W.cfg_fluid_L96()
+    with dpd.System.from_workload(w) as g:
+        g.set_variant(1)
+        assert dpd.variants()[1][:3] == (5, 4, 4)
+        g.step(3)
+        xg, vg, fg, t = g.get_state()
+    st = oracle.State.from_workload(w)
+    st.step(3)
+    dx = np.abs(_min_image_diff(xg, st.pos, w.L)).max()
+    dv = np.abs(vg - st.vel).max()
+    df = np.abs(fg - st.force).max()
+    print(f"fluid_L96 3 fused steps vs oracle: pos {dx:.3e} vel {dv:.3e} force {df:.3e}; "
+          f"momentum {np.abs(vg.sum(axis=0)).max():.3e}")
+    assert t == 3
+    assert dx <= TOL_X10["mixed"]
+    # Observed: pos 1.2e-7, vel 3.4e-6, force 5.6e-5 (deterministic on both sides).
+    assert dv <= 1e-4 and df <= TOL_F["mixed"]
+    assert np.abs(vg.sum(axis=0)).max() <= 1e-5 * np.sqrt(w.n) * np.abs(vg).max()
+
+
+def test_coincident_particles():
+    # Two particles exactly on top of each other: no force between them (e is
+    # undefined; Eq. 4 needs r > 0), the rest as the oracle has it; the pair
+    # count includes them.
+    w = W.fluid(5.0, seed=12)
+    w.pos[1] = w.pos[0]
+    for prec in ("mixed", "fp64"):
+        with dpd.System.from_workload(w, precision=prec) as g:
+            g.set_state(w.pos, w.vel, None, 0)
+            _, _, fg, _ = g.get_state()
+            o = g.observables()
+        fo = _oracle_force(w, 0)
+        assert np.all(np.isfinite(fg))
+        assert np.abs(fg - fo).max() <= TOL_F[prec]
+        ref = oracle.observables(w.pos, w.vel, w.L, w.types, w.a)
+        assert o["npairs"] == ref["npairs"]
+
+
 def test_full_size_pair_count_quantized():
     w = W.fluid(96.0, seed=3, quantize=8)
     with dpd.System.from_workload(w) as g:
