@@ -254,6 +254,11 @@ int dpd_footprint_bytes(const double L[3], int64_t n, int64_t nbonds, int precis
  *   dpd_batch_retire(b, slot)
  *       waits for the batch and hands the system back (usable as before, its
  *       step counter advanced); the slot and its bytes are freed.
+ *   dpd_batch_autotune(b, K, &best_variant, &ms_per_step)
+ *       runs one window of K steps with each brick variant (real steps: every
+ *       variant gives the same trajectory), times each on the device and keeps
+ *       the fastest; returns it and its time per step.  Best called once the
+ *       batch holds a representative set of replicas.  Synchronises.
  *   dpd_batch_info(b, out[6])
  *       resident replicas, bytes used, budget, graph captures, windows, variant.
  *   dpd_batch_destroy(b)
@@ -266,6 +271,7 @@ int dpd_batch_create(dpd_batch **out, int64_t budget_bytes, int max_replicas, vo
                      int variant);
 int dpd_batch_admit(dpd_batch *b, dpd_system *sys, int64_t nsteps, int *slot);
 int dpd_batch_advance(dpd_batch *b, int64_t K);
+int dpd_batch_autotune(dpd_batch *b, int64_t K, int *best_variant, double *ms_per_step);
 int dpd_batch_poll(dpd_batch *b, int *done, int max_done, int *ndone);
 int dpd_batch_retire(dpd_batch *b, int slot);
 int dpd_batch_info(dpd_batch *b, int64_t out[6]);

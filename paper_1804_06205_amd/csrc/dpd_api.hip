@@ -1017,6 +1017,8 @@ int batch_capture(dpd_batch *b, int K) {
     return DPD_OK;
 }
 
+void batch_split(dpd_batch *b, int slot);
+
 int batch_detach(dpd_batch *b, int slot) {
     if (int rc = batch_refresh(b)) return rc;
     dpd_system *s = b->sys[slot];
@@ -1136,13 +1138,11 @@ int dpd_batch_admit(dpd_batch *b, dpd_system *s, int64_t nsteps, int *slot) {
     BatchEnt e;
     std::memset(&e, 0, sizeof e);
     e.D = make_dev<float>(s);
-    e.nbx = (s->nc[0] + b->bx - 1) / b->bx;
-    e.nby = (s->nc[1] + b->by - 1) / b->by;
-    e.nbz = (s->nc[2] + b->bz - 1) / b->bz;
     const double lim = 536870912.0 / s->h[0];
     e.thr = (uint64_t)std::ceil(lim * lim);
     b->tab_h[k] = e;
     b->sys[k] = s;
+    batch_split(b, k);
     b->t0[k] = (uint32_t)s->t;
     b->target[k] = (uint32_t)(s->t + nsteps);
     b->err[k] = 0;
@@ -1155,7 +1155,33 @@ int dpd_batch_admit(dpd_batch *b, dpd_system *s, int64_t nsteps, int *slot) {
     return DPD_OK;
 }
 
-int dpd_batch_advance(dpd_batch *b, int64_t K) {
+}  // extern "C"
+
+namespace {
+
+// Bricks of a replica in the batch's current brick shape.
+void batch_split(dpd_batch *b, int slot) {
+    const dpd_system *s = b->sys[slot];
+    BatchEnt &e = b->tab_h[slot];
+    e.nbx = (s->nc[0] + b->bx - 1) / b->bx;
+    e.nby = (s->nc[1] + b->by - 1) / b->by;
+    e.nbz = (s->nc[2] + b->bz - 1) / b->bz;
+}
+
+void batch_set_variant(dpd_batch *b, int variant) {
+    int shape[5];
+    force_variant_shape(variant, shape);
+    b->variant = variant;
+    b->bx = shape[0];
+    b->by = shape[1];
+    b->bz = shape[2];
+    for (int k = 0; k < b->max_slots; ++k)
+        if (b->sys[k]) batch_split(b, k);
+    b->dirty = true;
+    b->graph_K = 0;       // re-capture with the new kernels
+}
+
+int batch_advance(dpd_batch *b, int64_t K, float *ms) {
     if (!b) return fail(DPD_EINVAL, "null batch");
     if (K < 1 || K > 100000) return fail(DPD_EINVAL, "window length must be in 1..100000");
     if (b->dirty) {
@@ -1168,14 +1194,55 @@ int dpd_batch_advance(dpd_batch *b, int64_t K) {
         HIP_OK(hipStreamSynchronize(b->stream));
         if (int rc = batch_capture(b, (int)K)) return rc;
     }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (ms) {
+        HIP_OK(hipEventCreate(&ev[0]));
+        HIP_OK(hipEventCreate(&ev[1]));
+        HIP_OK(hipEventRecord(ev[0], b->stream));
+    }
     HIP_OK(hipGraphLaunch(b->exec, b->stream));
+    if (ms) HIP_OK(hipEventRecord(ev[1], b->stream));
     HIP_OK(hipMemcpyAsync(b->status_h, b->status_dev, 2 * (size_t)b->max_slots * sizeof(uint32_t),
                           hipMemcpyDeviceToHost, b->stream));
     HIP_OK(hipEventRecord(b->done, b->stream));
     b->inflight = true;
     ++b->windows;
+    if (ms) {
+        HIP_OK(hipEventSynchronize(ev[1]));
+        HIP_OK(hipEventElapsedTime(ms, ev[0], ev[1]));
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
     // Replicas that reach their target keep their (now idle) work items until
     // the next admission or retirement rebuilds the lists.
+    return DPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpd_batch_advance(dpd_batch *b, int64_t K) { return batch_advance(b, K, nullptr); }
+
+int dpd_batch_autotune(dpd_batch *b, int64_t K, int *best_variant, double *best_ms) {
+    if (!b) return fail(DPD_EINVAL, "null batch");
+    if (K < 1 || K > 100000) return fail(DPD_EINVAL, "window length must be in 1..100000");
+    int best = b->variant;
+    double best_t = -1.0;
+    for (int v = 0; v < force_variant_count(); ++v) {
+        batch_set_variant(b, v);
+        float ms = -1.0f;
+        if (int rc = batch_advance(b, K, &ms)) return rc;
+        if (ms < 0.0f) break;               // nothing left to step
+        const double per = ms / (double)K;
+        if (best_t < 0.0 || per < best_t) {
+            best_t = per;
+            best = v;
+        }
+    }
+    batch_set_variant(b, best);
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t;
     return DPD_OK;
 }
 

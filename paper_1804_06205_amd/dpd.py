@@ -85,6 +85,8 @@ SIGNATURES = {
                                         ctypes.c_int]),
     "dpd_batch_admit": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int)]),
     "dpd_batch_advance": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "dpd_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_double)]),
     "dpd_batch_poll": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
     "dpd_batch_retire": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -313,6 +315,14 @@ class Batch:
 
     def advance(self, K: int):
         _check(lib().dpd_batch_advance(self._h, K))
+
+    def autotune(self, K: int = 20):
+        """One K-step window with each brick variant; keeps the fastest.
+        Returns (variant, ms per step)."""
+        v = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(lib().dpd_batch_autotune(self._h, K, ctypes.byref(v), ctypes.byref(ms)))
+        return v.value, ms.value
 
     def poll(self) -> list:
         """Waits for the enqueued windows; slots that finished since the last poll."""

@@ -56,11 +56,14 @@ def _summary(records, t_end: float, extra: dict) -> dict:
 
 def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: int = 1024,
                   variant: int = -1, cell_capacity: int = 0, make=workloads.replica,
-                  stream=None, realtime: bool = True):
+                  stream=None, realtime: bool = True, autotune_at: int = 64,
+                  autotune_window: int = 20):
     """Serves `requests` (workloads.Request, ascending arrival) through one batch.
 
-    Returns (records, summary).  With realtime=False every request is taken as
-    arrived at time 0 (a throughput run)."""
+    The first time `autotune_at` replicas are resident the batch's brick shape
+    is autotuned (a few short windows of real steps; 0 disables it).  Returns
+    (records, summary).  With realtime=False every request is taken as arrived
+    at time 0 (a throughput run)."""
     batch = dpd.Batch(budget_bytes, max_replicas, stream=stream, variant=variant)
     queue = deque(requests)
     prepared = deque()          # (record, system, footprint) created, not yet admitted
@@ -68,6 +71,7 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
     records = []
     used = 0                    # bytes of prepared + resident systems
     host = {"prepare": 0.0, "admit": 0.0, "advance": 0.0, "poll": 0.0, "retire": 0.0}
+    tuned = {"variant": None, "ms_per_step": None}
     t0 = time.perf_counter()
 
     def now():
@@ -133,6 +137,8 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
                 continue
             with _clock("advance"):
+                if autotune_at and tuned["variant"] is None and len(slot_of) >= autotune_at:
+                    tuned["variant"], tuned["ms_per_step"] = batch.autotune(autotune_window)
                 batch.advance(window)
             with _clock("prepare"):
                 prepare()           # overlaps the window on the GPU
@@ -160,7 +166,7 @@ def serve_batched(requests, budget_bytes: int, window: int = 100, max_replicas: 
                                               "graph_captures": info["captures"],
                                               "windows": info["windows"],
                                               "variant": info["variant"],
-                                              "host_s": host})
+                                              "autotuned": tuned, "host_s": host})
 
 
 def serve_one_at_a_time(requests, make=workloads.replica, cell_capacity: int = 0,

@@ -73,6 +73,37 @@ def test_replica_alone_equals_in_mix_bitwise(variant, window):
     assert info["windows"] >= 1
 
 
+def test_autotune_mid_run_keeps_trajectories_bitwise():
+    # The autotuner switches brick shapes between windows of real steps; every
+    # shape gives the same arithmetic, so each replica still ends bit for bit
+    # where it would alone.
+    reqs = [_req(30, 6, 10, 90), _req(31, 9, 30, 70), _req(32, 7, 20, 120)]
+    ws = [W.replica(r) for r in reqs]
+    systems = [dpd.System.from_workload(w) for w in ws]
+    out = {}
+    with dpd.Batch(1 << 34, 8) as b:
+        slot_of = {b.admit(g, r.steps): k for k, (g, r) in enumerate(zip(systems, reqs))}
+        b.advance(10)
+        v, ms = b.autotune(7)                  # five windows of 7 steps, one per shape
+        print(f"autotuned variant {v} ({ms * 1e3:.1f} us/step)", flush=True)
+        assert 0 <= v < len(dpd.variants()) and ms > 0
+        while len(out) < len(ws):
+            b.advance(16)
+            for slot in b.poll():
+                k = slot_of.pop(slot)
+                b.retire(slot)
+                out[k] = systems[k].get_state()
+    for g in systems:
+        g.close()
+    for k, (w, r) in enumerate(zip(ws, reqs)):
+        x0, v0, f0, t0 = _alone(w, r.steps)
+        x, v_, f, t = out[k]
+        assert t == t0 == r.steps
+        np.testing.assert_array_equal(x, x0)
+        np.testing.assert_array_equal(v_, v0)
+        np.testing.assert_array_equal(f, f0)
+
+
 def test_batched_replica_follows_oracle():
     w = W.replica(_req(7, 7, 30, 10))
     states, _ = _run_batch([w], [10], [0], window=4, variant=4)

@@ -57,6 +57,10 @@ class FakeBatch:
         for s in self.slots.values():
             s[0].t = min(s[0].t + K, s[1])
 
+    def autotune(self, K):
+        self.advance(K)
+        return 1, 0.01
+
     def poll(self):
         done = []
         for k, s in self.slots.items():
@@ -118,6 +122,14 @@ def test_fifo_admission_under_budget_and_all_complete(fake):
     assert summ["requests"] == 40
     assert summ["particle_steps"] == sum(3 * q.L ** 3 * q.steps for q in reqs)
     assert FakeSystem.live == 0                         # every system freed
+
+
+def test_autotune_runs_once_when_the_batch_fills(fake):
+    reqs = W.replica_stream(nreq=12, rate=1e6, seed=5, steps_range=(200, 400))
+    recs, summ = serve.serve_batched(reqs, 10 ** 9, window=50, make=FakeWorkload,
+                                     realtime=False, autotune_at=8, autotune_window=20)
+    assert summ["autotuned"]["variant"] == 1
+    assert len(recs) == 12 and all(np.isfinite(r.done) for r in recs)
 
 
 def test_windows_cover_the_longest_request(fake):
