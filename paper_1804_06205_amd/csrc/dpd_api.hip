@@ -7,8 +7,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dpd.h"
@@ -111,6 +114,7 @@ struct dpd_system {
     int cap = 32;
     int ntypes = 1;
     uint64_t seed = 0;
+    int dev = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
 
@@ -195,20 +199,170 @@ template <typename T> DevSys<T> make_dev(const dpd_system *s) {
     return D;
 }
 
+// ---------------------------------------------------------------------------
+// Reuse across systems.  hipFree waits for every stream of the device (a
+// batch window included), hipStreamCreate costs milliseconds, and pageable
+// host copies are slow, all measured on MI355X; a serving loop creates and
+// destroys systems while windows run.  So device blocks and streams of
+// destroyed systems are kept for later systems (blocks by size class, at most
+// REUSE_BYTES per device), and host arrays reach the device through one
+// pinned staging buffer.
+// ---------------------------------------------------------------------------
+struct Reuse {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void *>> blocks;   // (device, class)
+    std::map<void *, std::pair<int, size_t>> live;                  // block -> (device, class)
+    std::map<int, size_t> held;                                     // kept bytes per device
+    std::map<int, std::vector<hipStream_t>> streams;
+    std::mutex stage_mu;
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+};
+// Never destroyed: no HIP call may run from a static destructor at exit.
+Reuse &reuse() {
+    static Reuse *r = new Reuse();
+    return *r;
+}
+constexpr size_t REUSE_BYTES = (size_t)4 << 30;
+constexpr size_t REUSE_STREAMS = 64;
+constexpr size_t STAGE_MAX = (size_t)256 << 20;
+
+// Block size class: 4 KiB granules up to 64 KiB, then 16 classes per octave
+// (at most 1/8 over the request).
+size_t size_class(size_t b) {
+    if (b <= ((size_t)64 << 10)) return (b + 4095) & ~(size_t)4095;
+    size_t pw = 1;
+    while (pw < b) pw <<= 1;
+    const size_t step = pw / 16;
+    return (b + step - 1) / step * step;
+}
+
 int dmalloc(dpd_system *s, void **p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return fail(DPD_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    Reuse &r = reuse();
+    const size_t cls = size_class(bytes);
+    *p = nullptr;
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        auto it = r.blocks.find({s->dev, cls});
+        if (it != r.blocks.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            r.held[s->dev] -= cls;
+            r.live[*p] = {s->dev, cls};
+        }
+    }
+    if (!*p) {
+        hipError_t e = hipMalloc(p, cls);
+        if (e != hipSuccess) {
+            // Give the kept blocks of this device back and try once more.
+            std::vector<void *> drop;
+            {
+                std::lock_guard<std::mutex> g(r.mu);
+                for (auto &kv : r.blocks)
+                    if (kv.first.first == s->dev) {
+                        drop.insert(drop.end(), kv.second.begin(), kv.second.end());
+                        kv.second.clear();
+                    }
+                r.held[s->dev] = 0;
+            }
+            for (void *q : drop) (void)hipFree(q);
+            e = hipMalloc(p, cls);
+        }
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return fail(DPD_ENOMEM, "hipMalloc(%zu) failed: %s", cls, hipGetErrorString(e));
+        }
+        std::lock_guard<std::mutex> g(r.mu);
+        r.live[*p] = {s->dev, cls};
     }
     s->bytes += bytes;
     return DPD_OK;
 }
 
+// Keeps a block that no device work refers to any more for a later system.
+void dfree(void *p) {
+    if (!p) return;
+    Reuse &r = reuse();
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        auto it = r.live.find(p);
+        if (it != r.live.end()) {
+            const auto key = it->second;
+            r.live.erase(it);
+            if (r.held[key.first] + key.second <= REUSE_BYTES) {
+                r.blocks[key].push_back(p);
+                r.held[key.first] += key.second;
+                return;
+            }
+        }
+    }
+    (void)hipFree(p);
+}
+
+// The system's blocks go back once its stream is idle (a batch that held it
+// has already waited for its windows when it let the system go).
 void free_all(dpd_system *s) {
-    if (s->block) (void)hipFree(s->block);
-    if (s->bond_block) (void)hipFree(s->bond_block);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    dfree(s->block);
+    dfree(s->bond_block);
     s->block = s->bond_block = nullptr;
+}
+
+hipError_t stream_take(int dev, hipStream_t *st) {
+    Reuse &r = reuse();
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        auto &v = r.streams[dev];
+        if (!v.empty()) {
+            *st = v.back();
+            v.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+}
+
+// Returns a library-owned stream, once idle, for a later system.
+void release_stream(dpd_system *s) {
+    if (!s->own_stream || !s->stream) return;
+    (void)hipStreamSynchronize(s->stream);
+    Reuse &r = reuse();
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        auto &v = r.streams[s->dev];
+        if (v.size() < REUSE_STREAMS) {
+            v.push_back(s->stream);
+            s->stream = nullptr;
+            return;
+        }
+    }
+    (void)hipStreamDestroy(s->stream);
+    s->stream = nullptr;
+}
+
+// Host -> device copy of caller memory through the pinned staging buffer;
+// returns once the copy is complete (the buffer is reused by the next copy).
+int h2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return DPD_OK;
+    Reuse &r = reuse();
+    std::lock_guard<std::mutex> g(r.stage_mu);
+    if (bytes <= STAGE_MAX && r.stage_bytes < bytes) {
+        if (r.stage) (void)hipHostFree(r.stage);
+        r.stage = nullptr;
+        r.stage_bytes = 0;
+        size_t nb = (size_t)1 << 20;
+        while (nb < bytes) nb <<= 1;
+        if (hipHostMalloc(&r.stage, nb, hipHostMallocDefault) == hipSuccess) r.stage_bytes = nb;
+        else r.stage = nullptr;
+    }
+    if (r.stage_bytes >= bytes) {
+        std::memcpy(r.stage, src, bytes);
+        HIP_OK(hipMemcpyAsync(dst, r.stage, bytes, hipMemcpyHostToDevice, st));
+    } else {
+        HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    return DPD_OK;
 }
 
 // Reads the device error word; converts it to a sticky status.
@@ -240,8 +394,7 @@ int check_device(dpd_system *s) {
 
 template <typename T> int upload_params(dpd_system *s) {
     std::vector<T> a(s->a.begin(), s->a.end());
-    HIP_OK(hipMemcpyAsync(s->a_dev, a.data(), a.size() * sizeof(T), hipMemcpyHostToDevice,
-                          s->stream));
+    if (int rc = h2d(s->a_dev, a.data(), a.size() * sizeof(T), s->stream)) return rc;
     // Bond CSR over tags: each record appears at both of its ends.
     const int64_t n = s->n, nb = (int64_t)s->btype.size();
     if (nb > 0) {
@@ -268,14 +421,10 @@ template <typename T> int upload_params(dpd_system *s) {
         if (dmalloc(s, &s->bond_block, (size_t)bond_block_bytes(n, nb))) return DPD_ENOMEM;
         s->bond_off = (uint32_t *)s->bond_block;
         s->bonds = (char *)s->bond_block + align256((n + 1) * (int64_t)sizeof(uint32_t));
-        HIP_OK(hipMemcpyAsync(s->bond_off, off.data(), off.size() * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, s->stream));
-        HIP_OK(hipMemcpyAsync(s->bonds, ent.data(), ent.size() * sizeof(BondEnt<T>),
-                              hipMemcpyHostToDevice, s->stream));
-        // The host vectors must outlive the async copies.
-        HIP_OK(hipStreamSynchronize(s->stream));
-    } else {
-        HIP_OK(hipStreamSynchronize(s->stream));
+        if (int rc = h2d(s->bond_off, off.data(), off.size() * sizeof(uint32_t), s->stream))
+            return rc;
+        if (int rc = h2d(s->bonds, ent.data(), ent.size() * sizeof(BondEnt<T>), s->stream))
+            return rc;
     }
     return DPD_OK;
 }
@@ -317,13 +466,10 @@ int ensure_force(dpd_system *s) {
 int load_state(dpd_system *s, const double *pos, const double *vel, const double *frc,
                int64_t t) {
     const int64_t n = s->n;
-    HIP_OK(hipMemcpyAsync(s->stage, pos, 3 * n * sizeof(double), hipMemcpyHostToDevice,
-                          s->stream));
-    HIP_OK(hipMemcpyAsync(s->stage + 3 * n, vel, 3 * n * sizeof(double), hipMemcpyHostToDevice,
-                          s->stream));
+    if (int rc = h2d(s->stage, pos, 3 * n * sizeof(double), s->stream)) return rc;
+    if (int rc = h2d(s->stage + 3 * n, vel, 3 * n * sizeof(double), s->stream)) return rc;
     if (frc)
-        HIP_OK(hipMemcpyAsync(s->stage + 6 * n, frc, 3 * n * sizeof(double),
-                              hipMemcpyHostToDevice, s->stream));
+        if (int rc = h2d(s->stage + 6 * n, frc, 3 * n * sizeof(double), s->stream)) return rc;
     for (int k = 0; k < 3; ++k) HIP_OK(launch_fill_u32(s->count[k], s->ncells, 0u, s->stream));
     const uint32_t q = (uint32_t)t;
     if (s->prec == DPD_PREC_FP64)
@@ -399,6 +545,7 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
 
     dpd_system *s = new (std::nothrow) dpd_system();
     if (!s) return fail(DPD_ENOMEM, "host allocation failed");
+    s->dev = dev;
     s->prec = precision;
     s->n = n;
     s->ntypes = ntypes;
@@ -417,7 +564,7 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;
     } else {
-        hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        hipError_t e = stream_take(s->dev, &s->stream);
         if (e != hipSuccess) {
             delete s;
             return fail(DPD_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
@@ -451,7 +598,7 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
     s->red_blocks = red_blocks_for(n);
     if (rc) {
         free_all(s);
-        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        release_stream(s);
         delete s;
         return rc;
     }
@@ -461,11 +608,10 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
             HIP_OK(launch_fill_u32(s->slot_of_tag[k], n, 0u, s->stream));
         std::vector<uint8_t> tv(n, 0);
         if (type) std::memcpy(tv.data(), type, n);
-        HIP_OK(hipMemcpyAsync(s->type_dev, tv.data(), n, hipMemcpyHostToDevice, s->stream));
+        if (int rc = h2d(s->type_dev, tv.data(), n, s->stream)) return rc;
         double *ptrs[8] = {s->obs, s->obs + n, s->obs + 2 * n, s->obs + 3 * n, s->obs + 4 * n,
                            s->obs + 5 * n, s->obs + 6 * n, s->obs + 7 * n};
-        HIP_OK(hipMemcpyAsync(s->obs_ptrs, ptrs, sizeof ptrs, hipMemcpyHostToDevice, s->stream));
-        HIP_OK(hipStreamSynchronize(s->stream));
+        if (int rc = h2d(s->obs_ptrs, ptrs, sizeof ptrs, s->stream)) return rc;
         return load_state(s, pos, vel, nullptr, 0);
     };
     rc = setup();
@@ -473,7 +619,7 @@ int dpd_create(dpd_system **out, const double L[3], int64_t n, const double *pos
     if (rc) {
         std::string msg = g_err;
         free_all(s);
-        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        release_stream(s);
         delete s;
         return fail(rc, "%s", msg.c_str());
     }
@@ -826,7 +972,7 @@ void dpd_destroy(dpd_system *s) {
     if (s->batch) (void)batch_detach(s->batch, s->batch_slot);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     free_all(s);
-    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    release_stream(s);
     delete s;
 }
 
