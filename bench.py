@@ -33,7 +33,9 @@ HBM_PEAK_GBS = 8000.0
 B_ALG_MIXED = 112.0
 B_ALG_FP64 = 160.0
 # Plain 32-bit VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s).
-VALU_PEAK = 256 * 4 * 16 * 2.4e9
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+VALU_PEAK = SIMDS * 16 * CLOCK_HZ
 # Algorithmic lane-op slots per particle of the gather formulation at rho = 3:
 # 81 candidates x 8 (three differences, three 32x32->64 multiply-adds, one
 # compare, one accumulate) + 12.57 in-range pairs x 86 (Philox4x32-10 40,
@@ -41,21 +43,22 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # force 28).
 OPS_PER_PARTICLE = 81 * 8 + 12.57 * 86
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_fluid_L96_traffic.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_force_fluid_L96_counters.md")
 KERNEL_SOURCES = ["paper_1804_06205_amd/csrc/dpd_kernels.hip",
                   "paper_1804_06205_amd/csrc/dpd_device.hpp",
                   "paper_1804_06205_amd/csrc/dpd_kernels.hpp"]
 
 
-def measured_traffic(variant):
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    counter summary, if it was taken on these kernel sources and this brick."""
+def _profiled(path, key, variant):
+    """`key` of a committed rocprofv3 summary of the fused kernel, if it was
+    taken on these kernel sources and this brick."""
     import hashlib
     import re
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(path).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch=(\d+) variant=(\d+) sources_sha256=([0-9a-f]+)", txt)
+    m = re.search(key + r"=([0-9.]+) variant=(\d+) sources_sha256=([0-9a-f]+)", txt)
     if not m:
         return None
     h = hashlib.sha256()
@@ -65,6 +68,16 @@ def measured_traffic(variant):
     if h.hexdigest() != m.group(3) or int(m.group(2)) != variant:
         return None
     return float(m.group(1))
+
+
+def measured_traffic(variant):
+    """HBM bytes per launch of the fused kernel (FETCH_SIZE and WRITE_SIZE)."""
+    return _profiled(TRAFFIC_FILE, "traffic_bytes_per_launch", variant)
+
+
+def measured_valu(variant):
+    """Issued VALU wave instructions per particle of the fused kernel (SQ_INSTS_VALU)."""
+    return _profiled(COUNTERS_FILE, "valu_insts_per_particle", variant)
 
 
 def parse():
@@ -333,6 +346,7 @@ def main():
     achieved = b_alg * w.n / (fused_ms / 1e3) / 1e9
     alu = OPS_PER_PARTICLE * w.n / (fused_ms / 1e3)
     traffic = measured_traffic(variant) if w.name == "fluid_L96" else None
+    valu = measured_valu(variant) if w.name == "fluid_L96" else None
     info = g.info()
     obs = g.observables()
     g.close()
@@ -361,10 +375,16 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": "k_force (fused)", "kernel_ms": fused_ms,
-                     "bytes_per_particle_step": b_alg},
+                     "bytes_per_particle_step": b_alg,
+                     "binding_roof": "alu: VALU issue (roofline_alu)"},
         "roofline_alu": {"bound": "alu", "achieved": alu / 1e12, "peak": VALU_PEAK / 1e12,
                          "unit": "Tlane-op/s", "frac": alu / VALU_PEAK,
-                         "ops_per_particle_step": OPS_PER_PARTICLE},
+                         "ops_per_particle_step": OPS_PER_PARTICLE,
+                         # Issued VALU work (committed counter summary): the share of all
+                         # SIMD issue slots the kernel's VALU instructions take.
+                         "issued_valu_insts_per_particle": valu,
+                         "valu_issue_frac": None if valu is None else
+                         valu * 4 * w.n / (SIMDS * CLOCK_HZ * fused_ms / 1e3)},
         "kernel_ms": {"begin": kt["ms_begin"] / max(1, kt["n_begin"]), "fused": fused_ms,
                       "finish": kt["ms_finish"] / max(1, kt["n_finish"])},
         "final_kT": obs["kT"],
