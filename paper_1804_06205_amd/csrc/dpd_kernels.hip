@@ -202,9 +202,9 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
 // one particle i and walks the 9 rows of 3 consecutive halo cells that hold
 // its 27 neighbour cells, in a fixed order, so i adds its pair forces in the
 // same order on every run.  In-range neighbours are queued per lane in LDS and
-// the expensive pair term (Philox, Box-Muller, force) runs once three quarters
-// of the lanes hold a queued neighbour, which keeps the 64-wide wave busy
-// although only ~15% of the candidates are within the cutoff.
+// the expensive pair term (Philox, Box-Muller, force) runs once 15 of every 16
+// lanes hold a queued neighbour, which keeps the 64-wide wave busy although
+// only ~15% of the candidates are within the cutoff.
 //
 // IGEO (mixed precision, cubic cells): LDS holds brick-frame fixed-point
 // coordinates (cell offset + halo cell index, in units of 2^-29 cells, as
@@ -466,8 +466,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         // the queue as soon as it runs out (the read's latency then hides
         // behind the pair term).
         uint32_t cur = 0;
-        // Lanes with a particle; pending pairs are processed once 3/4 of them
-        // have one queued.
+        // Lanes with a particle; pending pairs are processed once
+        // DPD_ROUND_NUM / DPD_ROUND_DEN of them have one queued.
         const int nact = __popcll(__ballot(have));
         const int rth = max(1, (DPD_ROUND_NUM * nact) / DPD_ROUND_DEN);
 
