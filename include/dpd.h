@@ -27,9 +27,14 @@
  * reproducible bit for bit.
  *
  * Memory: the library copies every host array at the call and never keeps a
- * caller pointer.  It owns all device memory it allocates and frees it in
- * dpd_destroy.  Work is enqueued on one HIP stream per system (the caller's,
- * or one the library creates); dpd_step returns after enqueueing.
+ * caller pointer.  It owns all device memory it allocates and releases it in
+ * dpd_destroy, where a system's device block (and a stream the library
+ * created) is kept for reuse by later systems rather than returned to HIP:
+ * hipFree waits for every stream of the device, so freeing while other
+ * systems run would stall them.  At most 4 GiB of such blocks per device are
+ * kept, and all of them are returned to HIP before an allocation fails.  Work
+ * is enqueued on one HIP stream per system (the caller's, or one the library
+ * creates); dpd_step returns after enqueueing.
  *
  * Errors: every int-returning call returns DPD_OK (0) or a negative code and
  * leaves a message for dpd_last_error() (per thread).  Device-side failures
@@ -214,8 +219,9 @@ int dpd_autotune(dpd_system *sys, int trials, int *best_variant, double *best_ms
 int dpd_pair_noise(uint64_t seed, int64_t m, const uint32_t *tag_i, const uint32_t *tag_j,
                    const uint32_t *s, int precision, double *theta);
 
-/* Frees the system and its device memory (NULL is ignored).  A system still
- * resident in a batch is retired from it first. */
+/* Frees the system once its stream is idle; its device memory is kept for
+ * later systems (see Memory above).  NULL is ignored.  A system still resident
+ * in a batch is retired from it first. */
 void dpd_destroy(dpd_system *sys);
 
 /* Device bytes that dpd_create (plus dpd_add_bonds with nbonds records) will
