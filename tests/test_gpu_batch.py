@@ -215,3 +215,23 @@ def test_serve_small_stream_with_tight_budget():
     assert summ["graph_captures"] < summ["windows"]
     recs1, summ1 = serve.serve_one_at_a_time(reqs[:3])
     assert len(recs1) == 3 and summ1["particle_steps"] > 0
+
+
+def test_reused_device_blocks_do_not_change_results():
+    # A destroyed system's device block and stream go to the next system of
+    # the same size class; whatever the block held before must not matter.
+    wa = W.fluid(7.0, seed=41)
+    wb = W.fluid(7.0, seed=42)            # same size class as wa, other data
+    first = _alone(wb, 30)                # wb in whatever block it gets
+    with dpd.System.from_workload(wa) as g:
+        g.step(17)                        # leave wa's data in its block
+    second = _alone(wb, 30)               # wb again, now likely in wa's old block
+    for x, y in zip(first, second):
+        np.testing.assert_array_equal(x, y)
+    # Many creations and destructions of mixed sizes, then the same run again.
+    for k in range(12):
+        with dpd.System.from_workload(W.replica(_req(60 + k, 6 + k % 4, 10 + k, 5))) as g:
+            g.step(3)
+    third = _alone(wb, 30)
+    for x, y in zip(first, third):
+        np.testing.assert_array_equal(x, y)
