@@ -128,6 +128,30 @@ def test_force_parity_thermalised_state(precision):
     assert err <= TOL_F[precision]
 
 
+@pytest.mark.parametrize("n", [2, 3, 9])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_nearly_empty_box(n, precision):
+    # Almost every cell and most bricks hold nothing; n = 2 is the smallest
+    # system the boundary accepts.  Particles are placed in pairs within the
+    # cutoff so there are forces to compare.
+    w = W.fluid(7.0, seed=50 + n, precision=precision)
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(0, 7.0, (n, 3))
+    pos[1::2] = (pos[0:n - 1:2] + rng.uniform(-0.4, 0.4, (n // 2, 3))) % 7.0
+    w.pos, w.vel, w.types = pos, w.vel[:n].copy(), w.types[:n].copy()
+    fo = _oracle_force(w, 5)
+    assert np.abs(fo).max() > 0
+    err = np.abs(_gpu_force(w, precision, 5) - fo).max()
+    with dpd.System.from_workload(w, precision=precision) as g:
+        g.step(10)
+        xg, _, _, _ = g.get_state()
+    st = oracle.State.from_workload(w).step(10)
+    dx = np.abs(_min_image_diff(xg, st.pos, w.L)).max()
+    print(f"n={n} {precision}: force max-abs {err:.3e}, 10-step position {dx:.3e}", flush=True)
+    assert err <= TOL_F[precision]
+    assert dx <= TOL_X10[precision]
+
+
 def test_momentum_conservation():
     w = W.peptide(8.0, seed=12, nchains=6, nbeads=20)
     f = _gpu_force(w, "mixed", 3)
