@@ -19,7 +19,7 @@ def _declared():
     return sorted(set(re.findall(r"\b(dpd_[a-z_0-9]+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_step_path_calls():
     names = _declared()
     for must in ("dpd_create", "dpd_set_params", "dpd_add_bonds", "dpd_step",
                  "dpd_observables", "dpd_destroy"):
