@@ -31,6 +31,10 @@ namespace dpd {
 
 constexpr int QCAP = 8;          // per-lane pending-pair queue depth (>= 5)
 constexpr int MAXTYPES = 16;
+// Wave priority in the fused step: a brick's memory phases (cell counts,
+// staging, the epilogue's state loads and appends) issue ahead of other
+// waves' candidate scans, so their round trips start sooner.
+constexpr int PRIO_MEM = 3, PRIO_SCAN = 0;
 constexpr int MAXCHUNK = 32;     // neighbourhood chunks per brick
 // Pair rounds start once this fraction of a wave's lanes hold a pending pair.
 #ifndef DPD_ROUND_NUM
@@ -333,6 +337,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
 
     // The sticky error word is read with the halo counts (no round trip of
     // its own); a brick of a failed system stops after that phase.
+    if constexpr (IGEO && MODE == MODE_FUSED) __builtin_amdgcn_s_setprio(PRIO_MEM);
     if (tid == 0) s_flag = (int)*D.err;
 
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
@@ -570,6 +575,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                                                           chi, tile);
                 __syncthreads();
             }
+            if constexpr (IGEO && MODE == MODE_FUSED) __builtin_amdgcn_s_setprio(PRIO_SCAN);
             // Candidate scan: rows of three consecutive halo cells (clipped to
             // the chunk), four candidates per step with the LDS reads issued up
             // front; the step writes the free queue slot whether or not it
@@ -658,6 +664,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         }
 
         if (!have) continue;
+        if constexpr (IGEO && MODE == MODE_FUSED) __builtin_amdgcn_s_setprio(PRIO_MEM);
 
         // Bonds (Eq. 8): every record owned by this particle, in input order,
         // evaluated in FP64 (stiff Morse terms reach |F| ~ 1e2, where FP32
