@@ -31,8 +31,8 @@ namespace dpd {
 
 constexpr int QCAP = 8;          // per-lane pending-pair queue depth (>= 5)
 constexpr int MAXTYPES = 16;
-// Wave priority in the fused step: a brick's memory phases (cell counts,
-// staging, the epilogue's state loads and appends) issue ahead of other
+// Wave priority in the fused step: a brick's first phases (cell counts and
+// staging, chains of dependent memory round trips) issue ahead of other
 // waves' candidate scans, so their round trips start sooner.
 constexpr int PRIO_MEM = 3, PRIO_SCAN = 0;
 constexpr int MAXCHUNK = 32;     // neighbourhood chunks per brick
@@ -664,7 +664,6 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         }
 
         if (!have) continue;
-        if constexpr (IGEO && MODE == MODE_FUSED) __builtin_amdgcn_s_setprio(PRIO_MEM);
 
         // Bonds (Eq. 8): every record owned by this particle, in input order,
         // evaluated in FP64 (stiff Morse terms reach |F| ~ 1e2, where FP32
