@@ -250,47 +250,72 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, in
         const PRec<T> *src = D.P[lay] + halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc) * cap;
         const uint32_t hx = (uint32_t)(hc % HX), hy = (uint32_t)((hc / HX) % HY),
                        hz = (uint32_t)(hc / (HX * HY));
+        auto put = [&](const PRec<T> &r, int rank) __attribute__((always_inline)) {
+            AT a;
+            if constexpr (IGEO) {
+                a.qx = (uint32_t)r.ox + (hx << 29);
+                a.qy = (uint32_t)r.oy + (hy << 29);
+                a.qz = (uint32_t)r.oz + (hz << 29);
+            } else {
+                a.ox = r.ox;
+                a.oy = r.oy;
+                a.oz = r.oz;
+            }
+            a.tag = r.tag;
+            const int j = lo + rank;
+            tl.A[j] = a;
+            tl.vx[j] = r.vx;
+            tl.vy[j] = r.vy;
+            tl.vz[j] = r.vz;
+            tl.type[j] = (uint8_t)r.type;
+        };
+        // Cells of up to 8 records (nearly every cell at rho = 3): all their
+        // tags are read at once and ranked in registers, then the records are
+        // placed four at a time, instead of rereading the tags one load at a
+        // time for each group of four.  Larger cells still do that.
+        if (n <= 8) {
+            // Ranks as eight 4-bit fields, so the tags are dead before the
+            // records are loaded.
+            uint32_t rk = 0;
+            {
+                uint32_t tg[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) tg[u] = u < n ? src[u].tag : 0xFFFFFFFFu;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    uint32_t c = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) c += tg[k] < tg[u] ? 1u : 0u;
+                    rk |= c << (4 * u);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; c += 4) {
+                if (c >= n) break;
+                PRec<T> r[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c + u < n) r[u] = src[c + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c + u < n) put(r[u], (int)((rk >> (4 * (c + u))) & 0xFu));
+            }
+            continue;
+        }
         for (int k0 = 0; k0 < n; k0 += 4) {
             PRec<T> r[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (k0 + u < n) r[u] = src[k0 + u];
             int rank[4] = {0, 0, 0, 0};
-            if (n <= 4) {
+            for (int k = 0; k < n; ++k) {
+                const uint32_t tk = src[k].tag;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        rank[u] += (k < n && r[k].tag < r[u].tag) ? 1 : 0;
-            } else {
-                for (int k = 0; k < n; ++k) {
-                    const uint32_t tk = src[k].tag;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) rank[u] += tk < r[u].tag ? 1 : 0;
-                }
+                for (int u = 0; u < 4; ++u) rank[u] += tk < r[u].tag ? 1 : 0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (k0 + u < n) {
-                    AT a;
-                    if constexpr (IGEO) {
-                        a.qx = (uint32_t)r[u].ox + (hx << 29);
-                        a.qy = (uint32_t)r[u].oy + (hy << 29);
-                        a.qz = (uint32_t)r[u].oz + (hz << 29);
-                    } else {
-                        a.ox = r[u].ox;
-                        a.oy = r[u].oy;
-                        a.oz = r[u].oz;
-                    }
-                    a.tag = r[u].tag;
-                    const int j = lo + rank[u];
-                    tl.A[j] = a;
-                    tl.vx[j] = r[u].vx;
-                    tl.vy[j] = r[u].vy;
-                    tl.vz[j] = r[u].vz;
-                    tl.type[j] = (uint8_t)r[u].type;
-                }
-            }
+            for (int u = 0; u < 4; ++u)
+                if (k0 + u < n) put(r[u], rank[u]);
         }
     }
 }
