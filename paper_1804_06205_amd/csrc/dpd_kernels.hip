@@ -214,8 +214,11 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
 // coordinates (cell offset + halo cell index, in units of 2^-29 cells, as
 // u32), so a candidate's squared distance is an exact 64-bit integer and the
 // cutoff test is three subtractions and three 32x32->64 multiply-adds.
+// A lane walks its 9 rows back to back from a per-cell table of row ranges,
+// so a wave's scan lasts as long as its longest lane's candidate list.
 // Otherwise (FP64, or non-cubic cells) LDS holds cell-local offsets and the
-// whole-cell shift of each neighbour is applied explicitly.
+// whole-cell shift of each neighbour is applied explicitly; the wave steps
+// through the rows together.
 // ---------------------------------------------------------------------------
 struct alignas(16) LAI { uint32_t qx, qy, qz, tag; };
 
@@ -354,6 +357,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     // frame; index plus whole-cell shift code (u32) otherwise.
     using QT = typename std::conditional<IGEO, uint16_t, uint32_t>::type;
     __shared__ QT s_q[QCAP * NT];
+    // Integer frame: each own cell's candidate rows (see build_rows).
+    __shared__ uint32_t s_rows[IGEO ? NOC * 10 : 1];
 
     const int tid = threadIdx.x;
     const uint32_t lay = q & 1u;
@@ -449,6 +454,30 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     // r2 = 0, i.e. i itself (in the observables pass, which counts coincident
     // pairs too, i is excluded by tag instead).
     const uint64_t thr1 = thr - 1u;
+    // Integer frame: the nine candidate rows of every own cell (rows in
+    // (dz, dy) order, each three halo cells along x) as LDS ranges of the
+    // chunk [clo, chi): first | end << 16 | bit 31, then a zero entry.
+    // Built once per brick, or per chunk when the neighbourhood is split.
+    auto build_rows = [&](int clo, int chi, int off0) {
+        for (int e = tid; e < NOC * 10; e += NT) {
+            const int oc = e / 10, r = e - oc * 10;
+            uint32_t ent = 0u;
+            if (r < 9) {
+                const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
+                const int hr = ((oz + r / 3) * HY + (oy + r % 3)) * HX + ox;
+                const int r0 = max(hr, clo), r1 = min(hr + 3, chi);
+                int jb = 0, je = 0;
+                if (r0 < r1) {
+                    jb = s_hstart[r0] - off0;
+                    je = s_hstart[r1] - off0;
+                }
+                ent = (uint32_t)jb | ((uint32_t)je << 16) | 0x80000000u;
+            }
+            s_rows[e] = ent;
+        }
+    };
+    if constexpr (IGEO)
+        if (nchunk == 1) build_rows(0, NHC, 0);
 
     for (int base = 0; base < nown; base += NT) {
         const int qi = base + tid;
@@ -598,90 +627,109 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                 __syncthreads();
                 stage_cells<T, HX, HY, NT, IGEO, AT, HCAP>(D, lay, c0x, c0y, c0z, s_hstart, clo,
                                                           chi, tile);
+                if constexpr (IGEO) build_rows(clo, chi, off0);
                 __syncthreads();
             }
             if constexpr (IGEO && MODE == MODE_FUSED) __builtin_amdgcn_s_setprio(PRIO_SCAN);
-            // Candidate scan: rows of three consecutive halo cells (clipped to
-            // the chunk), four candidates per step with the LDS reads issued up
-            // front; the step writes the free queue slot whether or not it
+            // Candidate scan over rows of three consecutive halo cells (clipped
+            // to the chunk), four candidates per step with the LDS reads issued
+            // up front; the step writes the free queue slot whether or not it
             // found a pair, so it has no branches.  Before each step every
             // queue has room for what the step can add.
-            for (int row = 0; row < 9; ++row) {
-                const int dyc = row % 3 - 1, dzc = row / 3 - 1;
-                int jb = 0, b1 = 0, b2 = 0, je = 0;
-                if (have) {
-                    const int hr = ((ozc + 1 + dzc) * HY + (oyc + 1 + dyc)) * HX + oxc;
-                    const int r0 = max(hr, clo), r1 = min(hr + 3, chi);
-                    if (r0 < r1) {
-                        jb = s_hstart[r0] - off0;
-                        je = s_hstart[r1] - off0;
+            if constexpr (IGEO) {
+                // Each lane walks its own cell's nine rows back to back (the
+                // next row's entry read one row ahead), so the wave runs for
+                // its longest lane's total rather than each row's longest.
+                // Candidate order per lane is unchanged: rows, then cells,
+                // then LDS order.  A finished lane sits on its cell's zero
+                // entry (t = je = 0: in-bounds reads, empty masks).
+                const int oc = (ozc * BY + oyc) * BX + oxc;
+                const int rend = oc * 10 + 9;
+                int ri = have ? oc * 10 : rend;
+                uint32_t ent = s_rows[ri];
+                ri = min(ri + 1, rend);
+                uint32_t nxt = s_rows[ri];
+                int t = (int)(ent & 0xFFFFu), je = (int)((ent >> 16) & 0x7FFFu);
+                while (__ballot((int32_t)ent < 0)) {
+                    const AT *rowp = s_A + t;
+                    AT a[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] = rowp[u];
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int32_t ddx = (int32_t)(pqx - a[u].qx);
+                        const int32_t ddy = (int32_t)(pqy - a[u].qy);
+                        const int32_t ddz = (int32_t)(pqz - a[u].qz);
+                        // r^2 - 1 as an unsigned sum (each square < 2^62); the
+                        // -1 rides on the first multiply-add.
+                        const uint64_t r2m1 = (uint64_t)((int64_t)ddz * ddz - 1) +
+                                              (uint64_t)((int64_t)ddy * ddy) +
+                                              (uint64_t)((int64_t)ddx * ddx);
+                        bool hit;
+                        // The observables pass counts coincident pairs too
+                        // (r^2 = 0), excluding i by its tag.
+                        if (MODE == MODE_OBS) hit = (r2m1 + 1u < thr) & (a[u].tag != pi.tag);
+                        else hit = r2m1 < thr1;
+                        m |= (hit ? 1u : 0u) << u;
                     }
-                    if constexpr (!IGEO) {
+                    // Up to three reads past the row's end (into later cells or
+                    // the tile's padding) are dropped from the hit mask.
+                    m &= 0xFu >> (4 - min(max(je - t, 0), 4));
+                    const uint32_t entry = (uint32_t)t | (m << 12);
+                    const bool direct = (m != 0u) & (cur == 0u);
+                    myq[(qt % QCAP) * NT] = (QT)entry;     // free slot, used or not
+                    qt += ((m != 0u) & !direct) ? 1u : 0u;
+                    cur = direct ? entry : cur;
+                    t += 4;
+                    if (t >= je) {
+                        ent = nxt;
+                        t = (int)(ent & 0xFFFFu);
+                        je = (int)((ent >> 16) & 0x7FFFu);
+                        ri = min(ri + 1, rend);
+                        nxt = s_rows[ri];
+                    }
+                    if (__popcll(__ballot(cur != 0u)) >= rth) process();
+                    while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
+                }
+            } else {
+                // Offsets frame: one queue entry per in-range candidate, with
+                // its whole-cell shift code.
+                for (int row = 0; row < 9; ++row) {
+                    const int dyc = row % 3 - 1, dzc = row / 3 - 1;
+                    int jb = 0, b1 = 0, b2 = 0, je = 0;
+                    if (have) {
+                        const int hr = ((ozc + 1 + dzc) * HY + (oyc + 1 + dyc)) * HX + oxc;
+                        const int r0 = max(hr, clo), r1 = min(hr + 3, chi);
+                        if (r0 < r1) {
+                            jb = s_hstart[r0] - off0;
+                            je = s_hstart[r1] - off0;
+                        }
                         b1 = s_hstart[hr + 1] - off0;
                         b2 = s_hstart[hr + 2] - off0;
                     }
-                }
-                const int len = je - jb;
-                const uint32_t rowcode = (uint32_t)(((dyc + 1) << 2) | ((dzc + 1) << 4));
-                if constexpr (IGEO) {
-                    // Up to three reads past the row's end (into later cells
-                    // or the tile's padding) are dropped from the step's hit
-                    // mask, as are all four once a lane's row is done.
+                    const int len = je - jb;
+                    const uint32_t rowcode = (uint32_t)(((dyc + 1) << 2) | ((dzc + 1) << 4));
                     for (int t = 0; __ballot(t < len); t += 4) {
-                        const AT *rowp = s_A + jb + t;
                         AT a[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) a[u] = rowp[u];
-                        uint32_t m = 0;
+                        for (int u = 0; u < 4; ++u) a[u] = s_A[min(jb + t + u, max(je - 1, 0))];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const int32_t ddx = (int32_t)(pqx - a[u].qx);
-                            const int32_t ddy = (int32_t)(pqy - a[u].qy);
-                            const int32_t ddz = (int32_t)(pqz - a[u].qz);
-                            // r^2 - 1 as an unsigned sum (each square < 2^62); the
-                            // -1 rides on the first multiply-add.
-                            const uint64_t r2m1 = (uint64_t)((int64_t)ddz * ddz - 1) +
-                                                  (uint64_t)((int64_t)ddy * ddy) +
-                                                  (uint64_t)((int64_t)ddx * ddx);
-                            bool hit;
-                            // The observables pass counts coincident pairs too
-                            // (r^2 = 0), excluding i by its tag.
-                            if (MODE == MODE_OBS) hit = (r2m1 + 1u < thr) & (a[u].tag != pi.tag);
-                            else hit = r2m1 < thr1;
-                            m |= (hit ? 1u : 0u) << u;
+                            const int j = jb + t + u;
+                            const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
+                            const T dx = Geo<T>::delta(pi.ox, a[u].ox, sx, hxT);
+                            const T dy = Geo<T>::delta(pi.oy, a[u].oy, dyc, hyT);
+                            const T dz = Geo<T>::delta(pi.oz, a[u].oz, dzc, hzT);
+                            const bool hit = (dx * dx + dy * dy + dz * dz < (T)1) &
+                                             (t + u < len) & (a[u].tag != pi.tag);
+                            const uint32_t code = rowcode | (uint32_t)(sx + 1);
+                            myq[(qt % QCAP) * NT] = (QT)((uint32_t)j | (code << 16));
+                            qt += hit ? 1u : 0u;
                         }
-                        m &= 0xFu >> (4 - min(max(len - t, 0), 4));
-                        const uint32_t entry = (uint32_t)(jb + t) | (m << 12);
-                        const bool direct = (m != 0u) & (cur == 0u);
-                        myq[(qt % QCAP) * NT] = (QT)entry;     // free slot, used or not
-                        qt += ((m != 0u) & !direct) ? 1u : 0u;
-                        cur = direct ? entry : cur;
-                        if (__popcll(__ballot(cur != 0u)) >= rth) process();
-                        while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
+                        if (__popcll(__ballot(qt != qh)) >= rth) process();
+                        while (__ballot(qt - qh > (uint32_t)(QCAP - 4))) process();
                     }
-                } else {
-                // Offsets frame: one queue entry per in-range candidate, with
-                // its whole-cell shift code.
-                for (int t = 0; __ballot(t < len); t += 4) {
-                    AT a[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) a[u] = s_A[min(jb + t + u, max(je - 1, 0))];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int j = jb + t + u;
-                        const int sx = (j >= b1 ? 1 : 0) + (j >= b2 ? 1 : 0) - 1;
-                        const T dx = Geo<T>::delta(pi.ox, a[u].ox, sx, hxT);
-                        const T dy = Geo<T>::delta(pi.oy, a[u].oy, dyc, hyT);
-                        const T dz = Geo<T>::delta(pi.oz, a[u].oz, dzc, hzT);
-                        const bool hit = (dx * dx + dy * dy + dz * dz < (T)1) & (t + u < len) &
-                                         (a[u].tag != pi.tag);
-                        const uint32_t code = rowcode | (uint32_t)(sx + 1);
-                        myq[(qt % QCAP) * NT] = (QT)((uint32_t)j | (code << 16));
-                        qt += hit ? 1u : 0u;
-                    }
-                    if (__popcll(__ballot(qt != qh)) >= rth) process();
-                    while (__ballot(qt - qh > (uint32_t)(QCAP - 4))) process();
-                }
                 }
             }
             // Queue entries index this chunk's LDS contents: drain before the next.
