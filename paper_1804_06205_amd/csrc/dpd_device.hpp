@@ -35,6 +35,10 @@ template <> struct Geo<float> {
     __device__ static __forceinline__ P encode(double x, int c, double h) {
         return (int32_t)rint((x - (double)c * h) / h * SCALE);
     }
+    // encode(x, c, 1.0), without the divide.
+    __device__ static __forceinline__ P encode_unit(double x, int c) {
+        return (int32_t)rint((x - (double)c) * SCALE);
+    }
     // Separation along one axis: a - b - s cells, in length units (hs = h / 2^29).
     __device__ static __forceinline__ float delta(P a, P b, int s, float hs) {
         return (float)(a - b - s * ONE) * hs;
@@ -46,6 +50,7 @@ template <> struct Geo<double> {
     __device__ static __forceinline__ P encode(double x, int c, double h) {
         return x - (double)c * h;
     }
+    __device__ static __forceinline__ P encode_unit(double x, int c) { return x - (double)c; }
     __device__ static __forceinline__ double delta(P a, P b, int s, double h) {
         return (a - b) - (double)s * h;
     }
@@ -226,6 +231,14 @@ __device__ __forceinline__ double wrap_coord(double x, double L) {
 // Cell coordinate floor(x / h) with an IEEE FP64 divide, clamped to [0, n-1].
 __device__ __forceinline__ int cell_coord(double x, double h, int n) {
     int c = (int)floor(__ddiv_rn(x, h));
+    c = c > n - 1 ? n - 1 : c;
+    c = c < 0 ? 0 : c;
+    return c;
+}
+
+// cell_coord(x, 1.0, n), without the divide.
+__device__ __forceinline__ int cell_coord_unit(double x, int n) {
+    int c = (int)floor(x);
     c = c > n - 1 ? n - 1 : c;
     c = c < 0 ? 0 : c;
     return c;

@@ -160,9 +160,12 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
     z = wrap_coord(z + dz, D.L[2]);
     const T lt = D.lambda * D.dt;
     const T tx = vx + lt * fx, ty = vy + lt * fy, tz = vz + lt * fz;
-    const int cx = cell_coord(x, D.h[0], D.nc[0]);
-    const int cy = cell_coord(y, D.h[1], D.nc[1]);
-    const int cz = cell_coord(z, D.h[2], D.nc[2]);
+    // Unit cells (integer box edges, the usual case): x / 1 = x exactly, so
+    // the divides of the binning and the offset encoding drop out.
+    const bool unit = D.h[0] == 1.0 && D.h[1] == 1.0 && D.h[2] == 1.0;
+    const int cx = unit ? cell_coord_unit(x, D.nc[0]) : cell_coord(x, D.h[0], D.nc[0]);
+    const int cy = unit ? cell_coord_unit(y, D.nc[1]) : cell_coord(y, D.h[1], D.nc[1]);
+    const int cz = unit ? cell_coord_unit(z, D.nc[2]) : cell_coord(z, D.h[2], D.nc[2]);
     const int64_t g = cell_linear(cx, cy, cz, D.nc);
     const uint32_t k = atomicAdd(&D.count[qn % 3u][g], 1u);
     if (k >= (uint32_t)D.cap) {
@@ -172,9 +175,9 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
     const int64_t slot = g * D.cap + k;
     const uint32_t ln = qn & 1u;
     PRec<T> p;
-    p.ox = Geo<T>::encode(x, cx, D.h[0]);
-    p.oy = Geo<T>::encode(y, cy, D.h[1]);
-    p.oz = Geo<T>::encode(z, cz, D.h[2]);
+    p.ox = unit ? Geo<T>::encode_unit(x, cx) : Geo<T>::encode(x, cx, D.h[0]);
+    p.oy = unit ? Geo<T>::encode_unit(y, cy) : Geo<T>::encode(y, cy, D.h[1]);
+    p.oz = unit ? Geo<T>::encode_unit(z, cz) : Geo<T>::encode(z, cz, D.h[2]);
     p.tag = tag;
     p.vx = tx;
     p.vy = ty;
@@ -459,21 +462,23 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     // chunk [clo, chi): first | end << 16 | bit 31, then a zero entry.
     // Built once per brick, or per chunk when the neighbourhood is split.
     auto build_rows = [&](int clo, int chi, int off0) {
-        for (int e = tid; e < NOC * 10; e += NT) {
-            const int oc = e / 10, r = e - oc * 10;
-            uint32_t ent = 0u;
-            if (r < 9) {
-                const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
-                const int hr = ((oz + r / 3) * HY + (oy + r % 3)) * HX + ox;
-                const int r0 = max(hr, clo), r1 = min(hr + 3, chi);
-                int jb = 0, je = 0;
-                if (r0 < r1) {
-                    jb = s_hstart[r0] - off0;
-                    je = s_hstart[r1] - off0;
+        if constexpr (IGEO) {
+            for (int e = tid; e < NOC * 10; e += NT) {
+                const int oc = e / 10, r = e - oc * 10;
+                uint32_t ent = 0u;
+                if (r < 9) {
+                    const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
+                    const int hr = ((oz + r / 3) * HY + (oy + r % 3)) * HX + ox;
+                    const int r0 = max(hr, clo), r1 = min(hr + 3, chi);
+                    int jb = 0, je = 0;
+                    if (r0 < r1) {
+                        jb = s_hstart[r0] - off0;
+                        je = s_hstart[r1] - off0;
+                    }
+                    ent = (uint32_t)jb | ((uint32_t)je << 16) | 0x80000000u;
                 }
-                ent = (uint32_t)jb | ((uint32_t)je << 16) | 0x80000000u;
+                s_rows[e] = ent;
             }
-            s_rows[e] = ent;
         }
     };
     if constexpr (IGEO)
@@ -520,10 +525,10 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
         uint32_t qh = 0, qt = 0;
         // Integer frame: a queue entry is a group of four consecutive
         // candidates, base index | hit mask << 12; `cur` is the group being
-        // worked through.  cur == 0 only while the queue is empty: a group
-        // goes straight to cur when cur is empty, and cur is refilled from
-        // the queue as soon as it runs out (the read's latency then hides
-        // behind the pair term).
+        // worked through; it is empty when its mask is (cur < 2^12), which
+        // happens only while the queue is empty: a group goes straight to cur
+        // when cur is empty, and cur is refilled from the queue as soon as it
+        // runs out (the read's latency then hides behind the pair term).
         uint32_t cur = 0;
         // Lanes with a particle; pending pairs are processed once
         // DPD_ROUND_NUM / DPD_ROUND_DEN of them have one queued.
@@ -536,12 +541,10 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             int j = -1;
             uint32_t e = 0;
             if constexpr (IGEO) {
-                if (cur != 0u) {
-                    const uint32_t m = cur >> 12;
-                    j = (int)(cur & 0xFFFu) + __builtin_ctz(m);
-                    const uint32_t m2 = m & (m - 1u);
-                    cur = m2 ? ((cur & 0xFFFu) | (m2 << 12)) : 0u;
-                    if (cur == 0u && qt != qh) {
+                if (cur >= 0x1000u) {
+                    j = (int)(cur & 0xFFFu) + __builtin_ctz(cur >> 12);
+                    cur &= cur - 0x1000u;       // drop the lowest hit
+                    if (cur < 0x1000u && qt != qh) {
                         cur = (uint32_t)myq[(qh % QCAP) * NT];
                         ++qh;
                     }
@@ -677,7 +680,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                     // the tile's padding) are dropped from the hit mask.
                     m &= 0xFu >> (4 - min(max(je - t, 0), 4));
                     const uint32_t entry = (uint32_t)t | (m << 12);
-                    const bool direct = (m != 0u) & (cur == 0u);
+                    const bool direct = (m != 0u) & (cur < 0x1000u);
                     myq[(qt % QCAP) * NT] = (QT)entry;     // free slot, used or not
                     qt += ((m != 0u) & !direct) ? 1u : 0u;
                     cur = direct ? entry : cur;
@@ -689,7 +692,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         ri = min(ri + 1, rend);
                         nxt = s_rows[ri];
                     }
-                    if (__popcll(__ballot(cur != 0u)) >= rth) process();
+                    if (__popcll(__ballot(cur >= 0x1000u)) >= rth) process();
                     while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
                 }
             } else {
@@ -733,7 +736,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                 }
             }
             // Queue entries index this chunk's LDS contents: drain before the next.
-            while (__ballot(cur != 0u || qt != qh)) process();
+            while (__ballot(cur >= 0x1000u || qt != qh)) process();
         }
 
         if (!have) continue;
