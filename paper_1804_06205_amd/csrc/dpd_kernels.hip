@@ -459,7 +459,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     const uint64_t thr1 = thr - 1u;
     // Integer frame: the nine candidate rows of every own cell (rows in
     // (dz, dy) order, each three halo cells along x) as LDS ranges of the
-    // chunk [clo, chi): first | end << 16 | bit 31, then a zero entry.
+    // chunk [clo, chi): first | end << 16, then a zero entry.
     // Built once per brick, or per chunk when the neighbourhood is split.
     auto build_rows = [&](int clo, int chi, int off0) {
         if constexpr (IGEO) {
@@ -475,7 +475,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         jb = s_hstart[r0] - off0;
                         je = s_hstart[r1] - off0;
                     }
-                    ent = (uint32_t)jb | ((uint32_t)je << 16) | 0x80000000u;
+                    ent = (uint32_t)jb | ((uint32_t)je << 16);
                 }
                 s_rows[e] = ent;
             }
@@ -644,16 +644,16 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                 // next row's entry read one row ahead), so the wave runs for
                 // its longest lane's total rather than each row's longest.
                 // Candidate order per lane is unchanged: rows, then cells,
-                // then LDS order.  A finished lane sits on its cell's zero
-                // entry (t = je = 0: in-bounds reads, empty masks).
+                // then LDS order.  A finished lane (ri past its cell's zero
+                // entry) has t = je = 0: in-bounds reads, empty masks.
                 const int oc = (ozc * BY + oyc) * BX + oxc;
                 const int rend = oc * 10 + 9;
                 int ri = have ? oc * 10 : rend;
-                uint32_t ent = s_rows[ri];
-                ri = min(ri + 1, rend);
-                uint32_t nxt = s_rows[ri];
-                int t = (int)(ent & 0xFFFFu), je = (int)((ent >> 16) & 0x7FFFu);
-                while (__ballot((int32_t)ent < 0)) {
+                const uint32_t ent = s_rows[ri];
+                ++ri;                       // next entry; past rend once the lane is done
+                uint32_t nxt = s_rows[min(ri, rend)];
+                int t = (int)(ent & 0xFFFFu), je = (int)(ent >> 16);
+                while (__ballot(ri <= rend)) {
                     const AT *rowp = s_A + t;
                     AT a[4];
 #pragma unroll
@@ -677,8 +677,10 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         m |= (hit ? 1u : 0u) << u;
                     }
                     // Up to three reads past the row's end (into later cells or
-                    // the tile's padding) are dropped from the hit mask.
-                    m &= 0xFu >> (4 - min(max(je - t, 0), 4));
+                    // the tile's padding) are dropped from the hit mask; je >= t
+                    // (a row starts at or before its end, and the lane moves to
+                    // the next row as soon as t reaches je).
+                    m &= 0xFu >> (4 - min(je - t, 4));
                     const uint32_t entry = (uint32_t)t | (m << 12);
                     const bool direct = (m != 0u) & (cur < 0x1000u);
                     myq[(qt % QCAP) * NT] = (QT)entry;     // free slot, used or not
@@ -686,11 +688,10 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                     cur = direct ? entry : cur;
                     t += 4;
                     if (t >= je) {
-                        ent = nxt;
-                        t = (int)(ent & 0xFFFFu);
-                        je = (int)((ent >> 16) & 0x7FFFu);
-                        ri = min(ri + 1, rend);
-                        nxt = s_rows[ri];
+                        t = (int)(nxt & 0xFFFFu);
+                        je = (int)(nxt >> 16);
+                        ++ri;
+                        nxt = s_rows[min(ri, rend)];
                     }
                     if (__popcll(__ballot(cur >= 0x1000u)) >= rth) process();
                     while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
