@@ -653,6 +653,11 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                 ++ri;                       // next entry; past rend once the lane is done
                 uint32_t nxt = s_rows[min(ri, rend)];
                 int t = (int)(ent & 0xFFFFu), je = (int)(ent >> 16);
+                // -1 held in a scalar register the compiler cannot see into:
+                // it then stays the first multiply-add's addend instead of
+                // being reassociated into a separate 64-bit add per candidate.
+                uint64_t m1;
+                asm("s_mov_b64 %0, -1" : "=s"(m1));
                 while (__ballot(ri <= rend)) {
                     const AT *rowp = s_A + t;
                     AT a[4];
@@ -666,7 +671,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         const int32_t ddz = (int32_t)(pqz - a[u].qz);
                         // r^2 - 1 as an unsigned sum (each square < 2^62); the
                         // -1 rides on the first multiply-add.
-                        const uint64_t r2m1 = (uint64_t)((int64_t)ddz * ddz - 1) +
+                        const uint64_t r2m1 = (uint64_t)((int64_t)ddz * ddz) + m1 +
                                               (uint64_t)((int64_t)ddy * ddy) +
                                               (uint64_t)((int64_t)ddx * ddx);
                         bool hit;
