@@ -658,7 +658,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                 // being reassociated into a separate 64-bit add per candidate.
                 uint64_t m1;
                 asm("s_mov_b64 %0, -1" : "=s"(m1));
-                while (__ballot(ri <= rend)) {
+                // One step: four candidates of the lane's current row.
+                auto scan_step = [&]() __attribute__((always_inline)) {
                     const AT *rowp = s_A + t;
                     AT a[4];
 #pragma unroll
@@ -700,6 +701,14 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                     }
                     if (__popcll(__ballot(cur >= 0x1000u)) >= rth) process();
                     while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
+                };
+                // Two steps per trip: with one, the compiler copies the six
+                // values a pair round updates (cur, qt, qh, f) between two
+                // register sets on every step.
+                while (__ballot(ri <= rend)) {
+                    scan_step();
+                    if (!__ballot(ri <= rend)) break;
+                    scan_step();
                 }
             } else {
                 // Offsets frame: one queue entry per in-range candidate, with
