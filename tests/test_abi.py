@@ -76,3 +76,13 @@ def test_create_without_gpu_fails_cleanly():
         dpd.System([5.0] * 3, np.random.rand(10, 3) * 5, np.zeros((10, 3)))
     assert e.value.code == dpd.EDEVICE
     assert dpd.last_error()
+
+
+@pytest.mark.parametrize("n", [0, 1])
+def test_create_rejects_fewer_than_two_particles(n):
+    # Argument checks come before any device call, so this runs without a GPU.
+    import numpy as np
+    with pytest.raises(dpd.DPDError) as e:
+        dpd.System([5.0] * 3, np.random.rand(n, 3) * 5, np.zeros((n, 3)))
+    assert e.value.code == dpd.EINVAL
+    assert dpd.last_error()
