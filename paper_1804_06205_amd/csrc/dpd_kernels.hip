@@ -683,16 +683,18 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         m |= (hit ? 1u : 0u) << u;
                     }
                     // Up to three reads past the row's end (into later cells or
-                    // the tile's padding) are dropped from the hit mask; je >= t
-                    // (a row starts at or before its end, and the lane moves to
-                    // the next row as soon as t reaches je).
-                    m &= 0xFu >> (4 - min(je - t, 4));
+                    // the tile's padding) are dropped from the hit mask: by
+                    // t + 4 - je, clamped at 0 (one subtraction with clamp); it
+                    // is at most 4, as je >= t (a row starts at or before its
+                    // end, and the lane moves on as soon as t reaches je).
+                    const int tn = t + 4;
+                    m &= 0xFu >> __builtin_elementwise_sub_sat((uint32_t)tn, (uint32_t)je);
                     const uint32_t entry = (uint32_t)t | (m << 12);
                     const bool direct = (m != 0u) & (cur < 0x1000u);
                     myq[(qt % QCAP) * NT] = (QT)entry;     // free slot, used or not
                     qt += ((m != 0u) & !direct) ? 1u : 0u;
                     cur = direct ? entry : cur;
-                    t += 4;
+                    t = tn;
                     if (t >= je) {
                         t = (int)(nxt & 0xFFFFu);
                         je = (int)(nxt >> 16);
@@ -700,7 +702,13 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                         nxt = s_rows[min(ri, rend)];
                     }
                     if (__popcll(__ballot(cur >= 0x1000u)) >= rth) process();
-                    while (__ballot(qt - qh >= (uint32_t)QCAP)) process();
+                    // Rounds until every queue has room (two per trip, for the
+                    // same register-copy reason as the scan loop below).
+                    while (__ballot(qt - qh >= (uint32_t)QCAP)) {
+                        process();
+                        if (!__ballot(qt - qh >= (uint32_t)QCAP)) break;
+                        process();
+                    }
                 };
                 // Two steps per trip: with one, the compiler copies the six
                 // values a pair round updates (cur, qt, qh, f) between two
@@ -750,8 +758,13 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
                     }
                 }
             }
-            // Queue entries index this chunk's LDS contents: drain before the next.
-            while (__ballot(cur >= 0x1000u || qt != qh)) process();
+            // Queue entries index this chunk's LDS contents: drain before the
+            // next (two rounds per trip, as in the scan).
+            while (__ballot(cur >= 0x1000u || qt != qh)) {
+                process();
+                if (!__ballot(cur >= 0x1000u || qt != qh)) break;
+                process();
+            }
         }
 
         if (!have) continue;
