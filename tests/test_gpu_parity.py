@@ -268,6 +268,30 @@ def test_full_size_fused_steps_on_the_bench_brick():
     assert np.abs(vg.sum(axis=0)).max() <= 1e-5 * np.sqrt(w.n) * np.abs(vg).max()
 
 
+@pytest.mark.parametrize("cfg", ["melt_L32", "peptide_L40"])
+def test_full_size_bonded_configurations(cfg):
+    # The bonded configurations at their full sizes (98 304 and 192 000
+    # particles; harmonic bonds, and 1-3 / 1-5 standard Morse terms in the
+    # peptide): forces of the initial state, then three fused steps on the
+    # 5x4x4 brick, against the oracle.
+    w = {"melt_L32": W.cfg_melt_L32, "peptide_L40": W.cfg_peptide_L40}[cfg]()
+    fo = _oracle_force(w, 0)
+    with dpd.System.from_workload(w) as g:
+        g.set_variant(1)
+        g.set_state(w.pos, w.vel, None, 0)
+        _, _, fg, _ = g.get_state()
+        g.step(3)
+        xg, vg, _, t = g.get_state()
+    err = np.abs(fg - fo).max()
+    st = oracle.State.from_workload(w)
+    st.step(3)
+    dx = np.abs(_min_image_diff(xg, st.pos, w.L)).max()
+    dv = np.abs(vg - st.vel).max()
+    print(f"{cfg} (n={w.n}): force max-abs {err:.3e}; 3 steps pos {dx:.3e} vel {dv:.3e}")
+    assert err <= TOL_F["mixed"]
+    assert t == 3 and dx <= TOL_X10["mixed"] and dv <= 1e-3
+
+
 def test_coincident_particles():
     # Two particles exactly on top of each other: no force between them (e is
     # undefined; Eq. 4 needs r > 0), the rest as the oracle has it; the pair
