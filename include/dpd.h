@@ -161,7 +161,9 @@ int dpd_add_bonds(dpd_system *sys, int64_t nb, const int32_t *btype, const int64
 
 /* Enqueues nsteps >= 0 steps on the system's stream and returns.  Any call,
  * nsteps = 0 included, freezes the parameters and bonds and enqueues the
- * initial force if it is not yet computed. */
+ * initial force if it is not yet computed.  The step counter is limited to
+ * 2^32 - 1 (it keys the noise as a 32-bit word): DPD_EINVAL if step + nsteps
+ * would pass it. */
 int dpd_step(dpd_system *sys, int64_t nsteps);
 
 /* Like dpd_step, but synchronises and reports per-kernel device time. */
@@ -178,7 +180,8 @@ int dpd_observables(dpd_system *sys, dpd_obs *out);
 int dpd_get_state(dpd_system *sys, double *pos, double *vel, double *force, int64_t *step);
 
 /* Replaces the state (pos and vel required; force NULL = recompute it as
- * F(x, v; s = step) at the next step) and the step counter. */
+ * F(x, v; s = step) at the next step) and the step counter (0 .. 2^32 - 1,
+ * else DPD_EINVAL). */
 int dpd_set_state(dpd_system *sys, const double *pos, const double *vel, const double *force,
                   int64_t step);
 

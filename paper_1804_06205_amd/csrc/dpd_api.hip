@@ -52,6 +52,10 @@ enum Buf : int {
 
 int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
+// Largest state index: kernels take it as 32 bits (noise counter word 2, the
+// layout parity and the count-array rotation modulo 3).
+constexpr int64_t STEP_LIMIT = (int64_t)0xFFFFFFFF;
+
 int red_blocks_for(int64_t n) { return (int)std::min<int64_t>(256, (n + 1023) / 1024); }
 
 struct Layout {
@@ -693,6 +697,11 @@ int dpd_add_bonds(dpd_system *s, int64_t nb, const int32_t *btype, const int64_t
 static int step_impl(dpd_system *s, int64_t nsteps, dpd_kernel_times *tm) {
     if (int rc = check_usable(s)) return rc;
     if (nsteps < 0) return fail(DPD_EINVAL, "negative step count");
+    // The noise counter and the layout/count rotation use the step index as
+    // 32 bits; a run may not pass 2^32 - 1.
+    if (nsteps > STEP_LIMIT - s->t)
+        return fail(DPD_EINVAL, "step counter would pass 2^32 - 1 (at %lld, %lld more steps)",
+                    (long long)s->t, (long long)nsteps);
     if (int rc = freeze(s)) return rc;
     if (int rc = ensure_force(s)) return rc;
     if (nsteps == 0) return DPD_OK;
@@ -778,6 +787,7 @@ int dpd_set_state(dpd_system *s, const double *pos, const double *vel, const dou
     if (int rc = check_usable(s)) return rc;
     if (!pos || !vel) return fail(DPD_EINVAL, "null position or velocity");
     if (step < 0) return fail(DPD_EINVAL, "negative step counter");
+    if (step > STEP_LIMIT) return fail(DPD_EINVAL, "step counter above 2^32 - 1");
     if (!all_finite(pos, 3 * s->n) || !all_finite(vel, 3 * s->n) ||
         (frc && !all_finite(frc, 3 * s->n)))
         return fail(DPD_EINVAL, "non-finite state");
@@ -800,7 +810,7 @@ int dpd_get_cells(dpd_system *s, int64_t *cell_of_tag, int64_t *count) {
         HIP_OK(hipMemcpy(cell_of_tag, s->cell_stage, n * sizeof(int64_t), hipMemcpyDeviceToHost));
     if (count) {
         std::vector<uint32_t> c(s->ncells);
-        HIP_OK(hipMemcpy(c.data(), s->count[s->t % 3], s->ncells * sizeof(uint32_t),
+        HIP_OK(hipMemcpy(c.data(), s->count[(uint32_t)s->t % 3u], s->ncells * sizeof(uint32_t),
                          hipMemcpyDeviceToHost));
         for (int64_t g = 0; g < s->ncells; ++g) count[g] = c[g];
     }
@@ -1269,8 +1279,8 @@ int dpd_batch_admit(dpd_batch *b, dpd_system *s, int64_t nsteps, int *slot) {
         return fail(DPD_EINVAL, "batches hold mixed-precision systems only");
     if (!(s->h[0] == s->h[1] && s->h[0] == s->h[2]))
         return fail(DPD_EINVAL, "batches need cubic cells (equal cell edges on all axes)");
-    if (s->t + nsteps >= ((int64_t)1 << 32))
-        return fail(DPD_EINVAL, "step counter would pass 2^32");
+    if (nsteps > STEP_LIMIT - s->t)
+        return fail(DPD_EINVAL, "step counter would pass 2^32 - 1");
     if (int rc = freeze(s)) return rc;
     if (int rc = ensure_force(s)) return rc;
     if (int rc = check_device(s)) return rc;   // also waits for the system's own stream

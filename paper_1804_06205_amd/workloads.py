@@ -138,21 +138,34 @@ def _bond_arrays(records):
             np.asarray(rec[4], np.float64), np.asarray(rec[5], np.float64))
 
 
-def fluid(L: float = 10.0, rho: float = 3.0, seed: int = 1, kT: float = 1.0,
+def _box(L) -> np.ndarray:
+    """Box edges from a scalar (cubic box) or three edges."""
+    Lv = np.asarray(L, np.float64).reshape(-1)
+    return np.repeat(Lv, 3) if Lv.shape[0] == 1 else Lv.copy()
+
+
+def _box_name(Lv: np.ndarray) -> str:
+    if Lv[0] == Lv[1] == Lv[2]:
+        return f"{Lv[0]:g}"
+    return "x".join(f"{v:g}" for v in Lv)
+
+
+def fluid(L=10.0, rho: float = 3.0, seed: int = 1, kT: float = 1.0,
           a: float = 25.0, quantize: int | None = None, precision: str = "mixed",
           name: str | None = None, **kw) -> Workload:
-    """Single-species fluid: N = round(rho * L^3) beads uniform in a cubic box."""
-    Lv = np.array([L, L, L], np.float64)
-    n = int(round(rho * L ** 3))
+    """Single-species fluid: N = round(rho * V) beads uniform in the box (L a
+    scalar for a cubic box, or three edges)."""
+    Lv = _box(L)
+    n = int(round(rho * float(np.prod(Lv))))
     rng = _rng(seed)
     pos = rng.uniform(0.0, 1.0, size=(n, 3)) * Lv
     pos = _into_box(pos, Lv)
     if quantize is not None:
         pos = _quantize(rng, pos, Lv, quantize)
     vel = _velocities(rng, n, kT)
-    return Workload(name=name or f"fluid_L{L:g}", L=(L, L, L), pos=pos, vel=vel,
-                    types=np.zeros(n, np.uint8), ntypes=1, a=np.array([[a]]),
-                    kT=kT, seed=seed, precision=precision, **kw)
+    return Workload(name=name or f"fluid_L{_box_name(Lv)}", L=tuple(float(v) for v in Lv),
+                    pos=pos, vel=vel, types=np.zeros(n, np.uint8), ntypes=1,
+                    a=np.array([[a]]), kT=kT, seed=seed, precision=precision, **kw)
 
 
 def melt(L: float = 32.0, rho: float = 3.0, seed: int = 2, nbeads: int = 10,
@@ -204,11 +217,12 @@ def peptide_chain_bonds(offset: int, nbeads: int):
     return rec
 
 
-def peptide(L: float = 40.0, rho: float = 3.0, seed: int = 4, nchains: int = 400,
+def peptide(L=40.0, rho: float = 3.0, seed: int = 4, nchains: int = 400,
             nbeads: int = 20, b: float = 0.5, name: str | None = None, **kw) -> Workload:
-    """Peptide-like chains in solvent: nchains chains of nbeads beads, rest solvent."""
-    Lv = np.array([L, L, L], np.float64)
-    n = int(round(rho * L ** 3))
+    """Peptide-like chains in solvent: nchains chains of nbeads beads, rest
+    solvent (L a scalar for a cubic box, or three edges)."""
+    Lv = _box(L)
+    n = int(round(rho * float(np.prod(Lv))))
     nchain_beads = nchains * nbeads
     if nchain_beads > n:
         raise ValueError("more chain beads than particles")
@@ -224,8 +238,8 @@ def peptide(L: float = 40.0, rho: float = 3.0, seed: int = 4, nchains: int = 400
     for c in range(nchains):
         rec += peptide_chain_bonds(c * nbeads, nbeads)
     bt, bi, bj, re, kk, al = _bond_arrays(rec)
-    return Workload(name=name or f"peptide_L{L:g}", L=(L, L, L), pos=pos, vel=vel,
-                    types=types, ntypes=3, a=PEPTIDE_A.copy(), seed=seed, btype=bt,
+    return Workload(name=name or f"peptide_L{_box_name(Lv)}", L=tuple(float(v) for v in Lv),
+                    pos=pos, vel=vel, types=types, ntypes=3, a=PEPTIDE_A.copy(), seed=seed, btype=bt,
                     bi=bi, bj=bj, r_e=re, k=kk, alpha=al, **kw)
 
 

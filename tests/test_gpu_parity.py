@@ -68,6 +68,70 @@ def test_binning_matches_oracle_bit_exact(L):
     np.testing.assert_array_equal(count, ocount)
 
 
+def _cells_vs_oracle(g, x, L):
+    """The system's current cell list against the oracle's binning of the
+    system's own positions x: per-particle cells and counts, bit-exact."""
+    cell, count = g.get_cells()
+    cxyz, ocount, _, _ = oracle.bin_cells(x, L)
+    nc = np.floor(np.asarray(L, dtype=float)).astype(np.int64)
+    np.testing.assert_array_equal(cell, (cxyz[:, 2] * nc[1] + cxyz[:, 1]) * nc[0] + cxyz[:, 0])
+    np.testing.assert_array_equal(count, ocount)
+
+
+@pytest.mark.parametrize("case,steps,precision", [
+    ("fluid_L96", 5, "mixed"),             # unit cells: the divide-free binning
+    ("fluid_L7.5", 5, "mixed"),            # cell edge 7.5/7: the FP64 divide
+    ("fluid_L7.5", 5, "fp64"),
+    ("fluid_6x7.5x8", 6, "mixed"),         # non-cubic cells
+    ("peptide_L10", 7, "mixed"),
+])
+def test_binning_inside_steps_matches_oracle_bit_exact(case, steps, precision):
+    # After fused step passes, the cell list the kernels built (integrate-1 and
+    # the append into the next layout) equals the oracle's binning of the
+    # positions those passes produced.  steps = 1 goes through the begin pass
+    # only; more steps end with a list built by a fused pass.
+    w = {"fluid_L96": lambda: W.cfg_fluid_L96(),
+         "fluid_L7.5": lambda: W.fluid(7.5, seed=3),
+         "fluid_6x7.5x8": lambda: W.fluid((6.0, 7.5, 8.0), seed=9),
+         "peptide_L10": lambda: W.peptide(10.0, seed=10, nchains=8, nbeads=20)}[case]()
+    with dpd.System.from_workload(w, precision=precision) as g:
+        for k in (1, steps - 1):
+            g.step(k)
+            x, _, _, t = g.get_state(force=False)
+            _cells_vs_oracle(g, x, w.L)
+        assert t == steps
+
+
+def test_binning_of_exact_face_positions_inside_steps():
+    # No forces (a = gamma = sigma = 0), dt = 1/16, positions on a 2^-8 grid
+    # and velocities m/16: every drift dt v is exact, so particles move on the
+    # grid and land exactly on cell faces (and on 0 after wrapping from L)
+    # every step.  The kernels' positions equal the exact ballistic ones and
+    # their cells equal the oracle's, bit for bit, at every step.
+    L = 10.0
+    rng = np.random.default_rng(77)
+    n = 3000
+    pos = rng.integers(0, 256 * 10, size=(n, 3)).astype(np.float64) / 256.0
+    vel = rng.integers(-16, 17, size=(n, 3)).astype(np.float64) / 16.0
+    dt = 1.0 / 16.0
+    for precision in ("mixed", "fp64"):
+        with dpd.System([L] * 3, pos, vel, precision=precision) as g:
+            g.set_params([[0.0]], 0.0, 0.0, 1.0, dt, 0.65)
+            x = pos.copy()
+            faces = 0
+            for k in range(12):
+                g.step(1 if k % 2 == 0 else 3)
+                for _ in range(1 if k % 2 == 0 else 3):
+                    x = np.mod(x + dt * vel, L)
+                xg, vg, _, _ = g.get_state(force=False)
+                np.testing.assert_array_equal(xg, x)
+                np.testing.assert_array_equal(vg, vel)
+                faces += int((xg == np.floor(xg)).sum())
+                _cells_vs_oracle(g, xg, [L] * 3)
+        # About 3n / 256 = 35 coordinates sit exactly on a face per check.
+        assert faces > 200, (precision, faces)
+
+
 def test_non_cubic_box_binning():
     rng = np.random.default_rng(3)
     L = np.array([3.0, 4.5, 7.25])
@@ -103,6 +167,10 @@ def _cases():
         "melt_L8": W.melt(8.0, seed=4),
         "peptide_L8": W.peptide(8.0, seed=5, nchains=6, nbeads=20),
         "helix_L6": W.helix(6.0, seed=6, beads=12),
+        # Non-cubic cells (edges 1, 7.5/7, 1): the kernels' offsets frame
+        # with explicit whole-cell shifts, in both precisions.
+        "fluid_6x7.5x8": W.fluid((6.0, 7.5, 8.0), seed=7),
+        "peptide_6x7.5x8": W.peptide((6.0, 7.5, 8.0), seed=8, nchains=4, nbeads=20),
     }
 
 
@@ -164,7 +232,8 @@ def test_momentum_conservation():
 # Trajectories.
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["fluid_L10", "melt_L8", "peptide_L8", "helix_L6"])
+@pytest.mark.parametrize("name", ["fluid_L10", "melt_L8", "peptide_L8", "helix_L6",
+                                  "fluid_6x7.5x8", "peptide_6x7.5x8"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_ten_step_trajectory(name, precision):
     w = _cases()[name]
@@ -247,24 +316,25 @@ def test_full_size_fluid_binning_and_forces():
 
 def test_full_size_fused_steps_on_the_bench_brick():
     # The bench's launch configuration: the 5x4x4 brick, fused step passes,
-    # the full 2.65M-particle box; three steps against the oracle's.
+    # the full 2.65M-particle box; ten steps against the oracle's.
     w = W.cfg_fluid_L96()
     with dpd.System.from_workload(w) as g:
         g.set_variant(1)
         assert dpd.variants()[1][:3] == (5, 4, 4)
-        g.step(3)
+        g.step(10)
         xg, vg, fg, t = g.get_state()
     st = oracle.State.from_workload(w)
-    st.step(3)
+    st.step(10)
     dx = np.abs(_min_image_diff(xg, st.pos, w.L)).max()
     dv = np.abs(vg - st.vel).max()
     df = np.abs(fg - st.force).max()
-    print(f"fluid_L96 3 fused steps vs oracle: pos {dx:.3e} vel {dv:.3e} force {df:.3e}; "
+    print(f"fluid_L96 10 fused steps vs oracle: pos {dx:.3e} vel {dv:.3e} force {df:.3e}; "
           f"momentum {np.abs(vg.sum(axis=0)).max():.3e}")
-    assert t == 3
+    assert t == 10
     assert dx <= TOL_X10["mixed"]
-    # Observed: pos 1.2e-7, vel 3.4e-6, force 5.6e-5 (deterministic on both sides).
-    assert dv <= 1e-4 and df <= TOL_F["mixed"]
+    # Chaotic divergence grows the velocity and force differences with the
+    # step count; the force bar still holds after ten steps.
+    assert dv <= 1e-3 and df <= TOL_F["mixed"]
     assert np.abs(vg.sum(axis=0)).max() <= 1e-5 * np.sqrt(w.n) * np.abs(vg).max()
 
 
@@ -272,7 +342,7 @@ def test_full_size_fused_steps_on_the_bench_brick():
 def test_full_size_bonded_configurations(cfg):
     # The bonded configurations at their full sizes (98 304 and 192 000
     # particles; harmonic bonds, and 1-3 / 1-5 standard Morse terms in the
-    # peptide): forces of the initial state, then three fused steps on the
+    # peptide): forces of the initial state, then ten fused steps on the
     # 5x4x4 brick, against the oracle.
     w = {"melt_L32": W.cfg_melt_L32, "peptide_L40": W.cfg_peptide_L40}[cfg]()
     fo = _oracle_force(w, 0)
@@ -280,16 +350,16 @@ def test_full_size_bonded_configurations(cfg):
         g.set_variant(1)
         g.set_state(w.pos, w.vel, None, 0)
         _, _, fg, _ = g.get_state()
-        g.step(3)
+        g.step(10)
         xg, vg, _, t = g.get_state()
     err = np.abs(fg - fo).max()
     st = oracle.State.from_workload(w)
-    st.step(3)
+    st.step(10)
     dx = np.abs(_min_image_diff(xg, st.pos, w.L)).max()
     dv = np.abs(vg - st.vel).max()
-    print(f"{cfg} (n={w.n}): force max-abs {err:.3e}; 3 steps pos {dx:.3e} vel {dv:.3e}")
+    print(f"{cfg} (n={w.n}): force max-abs {err:.3e}; 10 steps pos {dx:.3e} vel {dv:.3e}")
     assert err <= TOL_F["mixed"]
-    assert t == 3 and dx <= TOL_X10["mixed"] and dv <= 1e-3
+    assert t == 10 and dx <= TOL_X10["mixed"] and dv <= 1e-2
 
 
 def test_coincident_particles():
@@ -341,6 +411,67 @@ def test_long_run_temperature_and_pressure():
     g.close()
     assert abs(np.mean(tg) - np.mean(to)) <= 0.01 * np.mean(to)
     assert abs(np.mean(pg) - np.mean(po)) <= 0.01 * np.mean(po)
+
+
+def test_long_run_temperature_and_pressure_mixed_precision():
+    # The mixed path (FP32 forces and velocities, hardware log/cos/rsqrt in the
+    # pair term) over a long run: peptide-like chains in solvent at L = 12
+    # (11 chains of 20, the peptide workload's 4% chain fraction), the
+    # standard 1-3 and 1-5 Morse terms at dt = 0.04, 2000 steps.  Time averages
+    # of kT and p after 200 steps agree with the oracle's within 1%, and the
+    # run stays stable (the stiff Morse at this dt).
+    w = W.peptide(12.0, seed=44, nchains=11, nbeads=20)
+    assert w.precision == "mixed"
+    g = dpd.System.from_workload(w)
+    st = oracle.State.from_workload(w)
+    g.step(200)
+    st.step(200)
+    tg, pg, to, po = [], [], [], []
+    for _ in range(360):
+        g.step(5)
+        st.step(5)
+        og = g.observables()
+        oo = st.observables()
+        tg.append(og["kT"])
+        pg.append(og["pressure"])
+        to.append(oo["kT"])
+        po.append(oo["pressure"])
+    xg, _, _, t = g.get_state(force=False)
+    g.close()
+    print(f"mixed long run: kT {np.mean(tg):.4f} vs {np.mean(to):.4f}, "
+          f"p {np.mean(pg):.3f} vs {np.mean(po):.3f}", flush=True)
+    assert t == 2000 and np.all(np.isfinite(xg))
+    assert abs(np.mean(tg) - np.mean(to)) <= 0.01 * np.mean(to)
+    assert abs(np.mean(pg) - np.mean(po)) <= 0.01 * np.mean(po)
+
+
+# --------------------------------------------------------------------------
+# The 32-bit step counter.
+# --------------------------------------------------------------------------
+
+def test_step_counter_limit():
+    # The step index keys the noise as a 32-bit word; the library runs up to
+    # 2^32 - 1 and refuses to pass it.  Near the limit the trajectory still
+    # follows the oracle and the cell list is the one of the current state.
+    w = W.peptide(6.0, seed=60, nchains=2, nbeads=12)
+    top = 2 ** 32 - 1
+    with dpd.System.from_workload(w) as g:
+        with pytest.raises(dpd.DPDError) as e:
+            g.set_state(w.pos, w.vel, None, top + 1)
+        assert e.value.code == dpd.EINVAL
+        g.set_state(w.pos, w.vel, None, top - 4)
+        g.step(4)
+        with pytest.raises(dpd.DPDError) as e:
+            g.step(1)
+        assert e.value.code == dpd.EINVAL
+        g.step(0)
+        x, v, f, t = g.get_state()
+        assert t == top
+        _cells_vs_oracle(g, x, w.L)
+    st = oracle.State(w.pos, w.vel, w.L, w.types, w.params(), w.seed, w.bonds(),
+                      step=top - 4).step(4)
+    assert np.abs(_min_image_diff(x, st.pos, w.L)).max() <= TOL_X10["mixed"]
+    assert np.abs(f - st.force).max() <= TOL_F["mixed"]
 
 
 # --------------------------------------------------------------------------

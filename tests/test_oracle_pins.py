@@ -34,13 +34,69 @@ def _params(a=25.0, gamma=4.5, sigma=3.0, dt=0.04, lam=0.65):
 # Pair force: closed forms (Eq. 4 and the F^D / F^R readings).
 # --------------------------------------------------------------------------
 
+def _exact_static(g):
+    """The two-particle closed form in exact rationals (x0 - x1 along -x only):
+    r = |dx|, e_x = sign(dx), w = 1 - r, F^C_0 = a w e, F^D_0 = -gamma w^2
+    (e . dv) e, U = a w^2 / 2, virial = d . F^C_0."""
+    from fractions import Fraction as Q
+    x0, x1 = Q(g["pos"][0][0]), Q(g["pos"][1][0])
+    v0, v1 = Q(g["vel"][0][0]), Q(g["vel"][1][0])
+    a, gamma = Q(g["a"]), Q(g["gamma"])
+    d = x0 - x1
+    r = abs(d)
+    e = 1 if d > 0 else -1
+    w = 1 - r
+    f0 = a * w * e - gamma * w * w * (e * (v0 - v1)) * e
+    return f0, a * w * w / 2, d * (a * w * e)
+
+
+def _exact_one_step(g):
+    """One step of Fig. 1 for two particles on the x axis with a = 0 and
+    sigma = 0 (only F^D acts), in exact rationals."""
+    from fractions import Fraction as Q
+    gamma, dt, lam = Q(g["gamma"]), Q(g["dt"]), Q(g["lambda"])
+    x = [Q(p[0]) for p in g["pos0"]]
+    v = [Q(p[0]) for p in g["vel0"]]
+
+    def force0(x, vt):
+        d = x[0] - x[1]
+        e = 1 if d > 0 else -1
+        w = 1 - abs(d)
+        return -gamma * w * w * (e * (vt[0] - vt[1])) * e
+
+    f = force0(x, v)
+    fx = [f, -f]
+    x1 = [x[k] + dt * v[k] + dt * dt / 2 * fx[k] for k in range(2)]
+    vt = [v[k] + lam * dt * fx[k] for k in range(2)]
+    f1 = force0(x1, vt)
+    fx1 = [f1, -f1]
+    v1 = [v[k] + dt / 2 * (fx[k] + fx1[k]) for k in range(2)]
+    return f, x1, f1, v1
+
+
+def test_golden_values_follow_from_exact_arithmetic():
+    # The stored values in tests/golden/two_particle.json are the exact
+    # rational results above, rounded to the digits stored.
+    g = _gold()
+    f0, u, wv = _exact_static(g["static"])
+    assert float(f0) == g["static"]["force"][0][0] and float(-f0) == g["static"]["force"][1][0]
+    assert float(u) == g["static"]["u_pair"] and float(wv) == g["static"]["w_pair"]
+    f, x1, f1, v1 = _exact_one_step(g["one_step"])
+    o = g["one_step"]
+    assert float(f) == o["force0_x"]
+    assert [float(q) for q in x1] == o["pos1_x"]
+    assert abs(float(f1) - o["force1_x"]) < 5e-12
+    assert all(abs(float(a) - b) < 5e-14 for a, b in zip(v1, o["vel1_x"]))
+
+
 def test_two_particle_conservative_and_dissipative():
     g = _gold()["static"]
+    f0, u, wv = _exact_static(g)
     F, U, Wv, npairs = oracle.pair_forces(g["pos"], g["vel"], [g["L"]] * 3, g["a"], g["gamma"],
                                           g["sigma"], g["dt"], seed=1, s=0)
-    np.testing.assert_allclose(F, g["force"], rtol=0, atol=1e-12)
-    assert abs(U - g["u_pair"]) < 1e-12
-    assert abs(Wv - g["w_pair"]) < 1e-12
+    np.testing.assert_allclose(F, [[float(f0), 0, 0], [float(-f0), 0, 0]], rtol=0, atol=1e-12)
+    assert abs(U - float(u)) < 1e-12
+    assert abs(Wv - float(wv)) < 1e-12
     assert npairs == 1
 
 
@@ -305,14 +361,15 @@ def test_wrap_rule():
 
 def test_one_step_uses_lambda_predictor():
     g = _gold()["one_step"]
+    f0, x1, f1, v1 = _exact_one_step(g)
     par = dict(a=np.array([[g["a"]]]), gamma=g["gamma"], sigma=g["sigma"], kT=1.0, dt=g["dt"],
                lam=g["lambda"])
     st = oracle.State(g["pos0"], g["vel0"], [g["L"]] * 3, None, par, seed=1)
-    assert abs(st.force[0, 0] - g["force0_x"]) < 1e-14
+    assert abs(st.force[0, 0] - float(f0)) < 1e-14
     st.step(1)
-    np.testing.assert_allclose(st.pos[:, 0], g["pos1_x"], atol=1e-14)
-    assert abs(st.force[0, 0] - g["force1_x"]) < 1e-12
-    np.testing.assert_allclose(st.vel[:, 0], g["vel1_x"], atol=1e-13)
+    np.testing.assert_allclose(st.pos[:, 0], [float(q) for q in x1], atol=1e-14)
+    assert abs(st.force[0, 0] - float(f1)) < 1e-12
+    np.testing.assert_allclose(st.vel[:, 0], [float(q) for q in v1], atol=1e-13)
 
 
 def test_harmonic_dimer_matches_verlet_closed_form():
@@ -343,32 +400,44 @@ def test_harmonic_dimer_matches_verlet_closed_form():
                                atol=1e-11)
 
 
-def _energy_series(dt, nsteps, every):
+def _energy_rms_and_drift(seed, dt, t_total=20.0, t_every=0.1):
+    """gamma = sigma = 0 from a state relaxed with the thermostat (relaxation
+    noise seed `seed`): the RMS of E_tot about its least-squares line, sampled
+    every t_every over t_total time units, and |E(t_total) - E(0)|, with the
+    kinetic energy at the end."""
     w = W.fluid(5.0, seed=31)
-    par = _params(gamma=0.0, sigma=0.0, dt=dt)
-    # Relax the random start with the thermostat first, then switch it off.
-    st = oracle.State(w.pos, w.vel, w.L, None, _params(dt=0.02), seed=4)
+    st = oracle.State(w.pos, w.vel, w.L, None, _params(dt=0.02), seed=seed)
     st.step(300)
-    st = oracle.State(st.pos, st.vel, w.L, None, par, seed=4)
-    E = []
-    for _ in range(nsteps // every):
+    st = oracle.State(st.pos, st.vel, w.L, None, _params(gamma=0.0, sigma=0.0, dt=dt), seed=seed)
+    every = int(round(t_every / dt))
+    E = [st.observables()["e_total"]]
+    for _ in range(int(round(t_total / dt)) // every):
         st.step(every)
         E.append(st.observables()["e_total"])
-    return np.array(E), st
+    E = np.array(E)
+    t = np.arange(E.shape[0], dtype=float)
+    rms = float(np.sqrt(np.mean((E - np.polyval(np.polyfit(t, E, 1), t)) ** 2)))
+    return rms, abs(E[-1] - E[0]), st.observables()["ke"]
 
 
 def test_energy_conservation_without_thermostat():
-    # gamma = sigma = 0: velocity Verlet on a smooth potential conserves energy
-    # to O(dt^2) with no drift; halving dt shrinks the fluctuation about 4x.
-    # The force kink at r = 1 leaves a small random-walk drift; over 20 time
-    # units at dt = 0.01 it stays below 1e-3 of the kinetic energy.
-    E1, _ = _energy_series(0.02, 1000, 5)
-    E2, st = _energy_series(0.01, 2000, 10)
-    ke = st.observables()["ke"]
-    assert abs(E2[-1] - E2[0]) < 1e-3 * ke
-    amp1 = E1.max() - E1.min()
-    amp2 = E2.max() - E2.min()
-    assert 3.0 < amp1 / amp2 < 5.0
+    # gamma = sigma = 0: velocity Verlet (Fig. 1 with the thermostat off) on
+    # the soft potential conserves energy to O(dt^2): the fluctuation of E_tot
+    # about its trend scales as dt^2.  The statistic is the log-log slope of
+    # that RMS over dt = 0.02, 0.01, 0.005, averaged over six relaxation seeds
+    # (per seed the slope scatters with sd ~0.25 around 2.0, so the six-seed
+    # mean has sd ~0.1 and the bar [1.6, 2.4] is four of them).  A first-order
+    # integrator gives a slope near 1.  The force kink at r = 1 adds a small
+    # random-walk drift; at dt = 0.005 it stays below 1e-3 of the kinetic
+    # energy over 20 time units for every seed (observed at most 1.4e-4).
+    dts = (0.02, 0.01, 0.005)
+    slopes = []
+    for seed in range(4, 10):
+        res = [_energy_rms_and_drift(seed, dt) for dt in dts]
+        slopes.append(np.polyfit(np.log(dts), np.log([r[0] for r in res]), 1)[0])
+        rms, drift, ke = res[-1]
+        assert drift < 1e-3 * ke, (seed, drift, ke)
+    assert 1.6 < float(np.mean(slopes)) < 2.4, slopes
 
 
 # --------------------------------------------------------------------------
@@ -395,12 +464,15 @@ def test_equipartition_dense_fluid():
 
 def test_equipartition_ideal_gas_small_dt():
     # a = 0: the ideal gas reaches kT = 1 as dt -> 0 (at dt = 0.04 it runs
-    # about 1.4% hot); p = rho kT exactly since the virial vanishes.
+    # about 1.4% hot, at dt = 0.01 about 0.26%); p = rho kT exactly since the
+    # virial vanishes.  Over 18 seeds one seed's mean scatters with sd 0.0058,
+    # so the six-seed mean has sd 0.0024 and the bar 0.01 sits 3.1 sd above
+    # the observed +0.0026 offset.
     ms = []
-    for seed in (100, 101, 102):
+    for seed in range(100, 106):
         m, st, w = _mean_kT(0.0, 0.01, seed, 10.0, 30.0)
         ms.append(m)
-    assert abs(np.mean(ms) - 1.0) < 0.006
+    assert abs(np.mean(ms) - 1.0) < 0.01
     o = st.observables()
     assert o["w_pair"] == 0.0
     assert abs(o["pressure"] - o["kT"] * (w.n - 1) / o["volume"]) < 1e-12
@@ -531,3 +603,27 @@ def test_philox_matches_rocrand_engine():
         ctr[1] >>= 2          # rocRAND's offset counts words in 64 bits
         key = [seed & 0xFFFFFFFF, seed >> 32]
         np.testing.assert_array_equal(oracle.philox4x32_10(ctr, key), ref(seed, ctr))
+
+
+def test_pair_noise_stream_layout_known_answers():
+    # The noise stream reading: Philox4x32-10 keyed by (seed mod 2^32,
+    # seed >> 32) at counter (min tag, max tag, s, 0); u1 = ((w0 >> 8) + 1)
+    # 2^-24, u2 = (w1 >> 8) 2^-24, theta = sqrt(-2 ln u1) cos(2 pi u2).  The raw
+    # words come from rocRAND's engine, the uniforms and Box-Muller are taken
+    # here, so a slip in which word carries the tags, the step or a key half,
+    # in the 8-bit shift or in the +1 offset of u1 changes theta.
+    from philox_ref import philox4x32_10 as ref
+    rng = np.random.default_rng(23)
+    for _ in range(400):
+        seed = int(rng.integers(0, 2 ** 63))
+        ti, tj = (int(v) for v in rng.integers(0, 2 ** 30, size=2))
+        s = int(rng.integers(0, 2 ** 32))
+        w = ref(seed, [min(ti, tj), max(ti, tj), s, 0])
+        u1 = ((int(w[0]) >> 8) + 1) * 2.0 ** -24
+        u2 = (int(w[1]) >> 8) * 2.0 ** -24
+        expect = math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+        got = oracle.pair_noise(seed, ti, tj, s)
+        assert abs(got - expect) <= 1e-13 * max(1.0, abs(expect)), (seed, ti, tj, s)
+    # Extreme words: the largest u1 is exactly 1 (theta = 0) and u1 never
+    # reaches 0, so theta stays finite; the step enters modulo 2^32.
+    assert oracle.pair_noise(5, 3, 9, 2 ** 32 + 7) == oracle.pair_noise(5, 3, 9, 7)
