@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="fluid_L96",
                     choices=["fluid_L96", "fluid_L10", "melt_L32", "peptide_L40",
-                             "replica_stream", "paper_sweep"])
+                             "replica_stream", "paper_sweep", "configs"])
     ap.add_argument("--window", type=int, default=100,
                     help="replica_stream: steps per batch window")
     ap.add_argument("--budget-gib", type=float, default=64.0,
@@ -96,6 +96,9 @@ def parse():
                     help="replica_stream: requests replayed")
     ap.add_argument("--no-serial", action="store_true",
                     help="replica_stream: skip the one-at-a-time baseline")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="fluid_L96: skip the serving leg (the replica stream, batched "
+                         "and one at a time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=None,
@@ -139,6 +142,38 @@ def cpu_baseline(w, budget_s):
             "kind": "oracle", "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(),
             "sample": f"{steps} step(s) of the same {w.name} box ({w.n} particles) after its "
                       f"initial force, FP64, {threads} OpenMP threads, {el:.1f} s"}
+
+
+SERVING_KEYS = ("requests", "makespan_s", "particle_steps", "particle_steps_per_s",
+                "replica_steps_per_s", "latency_p50_s", "latency_p99_s", "latency_max_s")
+
+
+def serving_leg(args):
+    """The serving half of the metric: the 512-request replica stream (Poisson
+    arrivals at 200/s, L in 6..12, one 10-40 bead chain each, 1000-10000
+    steps) served by continuous batching, and the same trace one replica at a
+    time through dpd_step (first come first served)."""
+    from paper_1804_06205_amd import serve
+    from paper_1804_06205_amd import workloads as W
+
+    reqs = W.replica_stream()[: args.requests]
+    budget = int(args.budget_gib * (1 << 30))
+    serve.serve_batched(W.replica_stream(nreq=4, steps_range=(50, 100)), budget,
+                        window=args.window, realtime=False)
+    _, summ = serve.serve_batched(reqs, budget, window=args.window)
+    out = {"workload": "replica_stream", "arrival_rate_per_s": 200.0, "L": [6, 12],
+           "chain_beads": [10, 40], "steps": [1000, 10000], "window": args.window,
+           "batched": {k: summ[k] for k in SERVING_KEYS}}
+    out["batched"]["variant"] = summ["variant"]
+    out["batched"]["graph_captures"] = summ["graph_captures"]
+    if not args.no_serial:
+        _, s1 = serve.serve_one_at_a_time(reqs)
+        out["one_at_a_time"] = {k: s1[k] for k in SERVING_KEYS}
+        out["speedup_particle_steps"] = (summ["particle_steps_per_s"] /
+                                         s1["particle_steps_per_s"])
+        out["p99_ratio_one_at_a_time_over_batched"] = (s1["latency_p99_s"] /
+                                                       summ["latency_p99_s"])
+    return out
 
 
 def replica_stream(args):
@@ -284,6 +319,67 @@ def paper_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+CONFIG_SET = (("fluid_L10", 100), ("melt_L32", 1000), ("peptide_L40", 2000),
+              ("fluid_L96", 500))
+
+
+def configs(args):
+    """Every benchmark workload at its full step count: time per step through
+    dpd_step (eager launches) and, for the mixed-precision ones, through a
+    one-replica batch whose windows of 100 steps replay a captured HIP graph;
+    the fused kernel's share of the step (per-launch device times)."""
+    import torch
+    from paper_1804_06205_amd import dpd
+
+    rows = []
+    for name, steps in CONFIG_SET:
+        w = make_workload(name)
+        stream = torch.cuda.Stream()
+        g = dpd.System.from_workload(w, stream=stream)
+        g.step(args.warmup)
+        g.sync()
+        if w.precision == "mixed":
+            variant, _ = g.autotune(3)
+        else:
+            variant = g.info().get("variant", None)
+        ms = _gpu_ms_per_step(g, steps, stream)
+        kt = g.step_profiled(min(steps, 200))
+        obs = g.observables()
+        g.close()
+        row = {"workload": name, "particles": w.n, "steps": steps, "precision": w.precision,
+               "us_per_step": ms * 1e3, "particle_steps_per_s": w.n / ms * 1e3,
+               "fused_kernel_us": kt["ms_fused"] / max(1, kt["n_fused"]) * 1e3,
+               "begin_kernel_us": kt["ms_begin"] / max(1, kt["n_begin"]) * 1e3,
+               "fused_share": (kt["ms_fused"] / max(1, kt["n_fused"])) / ms,
+               "final_kT": obs["kT"], "final_pressure": obs["pressure"]}
+        if w.precision == "mixed":
+            row["brick"] = list(dpd.variants()[variant][:3])
+            K = 100
+            g = dpd.System.from_workload(w)
+            with dpd.Batch(1 << 40, 1, variant=variant) as b:
+                b.admit(g, 10 ** 7)
+                b.advance(K)
+                b.poll()
+                nwin = max(1, steps // K)
+                t0 = time.perf_counter()
+                for _ in range(nwin):
+                    b.advance(K)
+                b.poll()
+                ms_graph = (time.perf_counter() - t0) * 1e3 / (nwin * K)
+            g.close()
+            row["graph_us_per_step"] = ms_graph * 1e3
+            row["graph_gain"] = ms / ms_graph
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    line = {"metric": "particle-steps/s (DPD step, rho=3)", "value": rows[-1]["particle_steps_per_s"],
+            "unit": "particle-steps/s", "n_gpus": 1, "steps": None, "warmup": args.warmup,
+            "ms_per_step": rows[-1]["us_per_step"] / 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "configs", "set": [r["workload"] for r in rows]},
+            "rows": rows, "roofline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -300,6 +396,9 @@ def main():
         return
     if args.workload == "paper_sweep":
         paper_sweep(args)
+        return
+    if args.workload == "configs":
+        configs(args)
         return
     w = make_workload(args.workload)
     stream = torch.cuda.Stream()
@@ -392,6 +491,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    if w.name == "fluid_L96" and not args.no_serving:
+        line["serving"] = serving_leg(args)
     print(json.dumps(line), flush=True)
 
 

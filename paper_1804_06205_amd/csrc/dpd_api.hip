@@ -810,7 +810,7 @@ int dpd_get_cells(dpd_system *s, int64_t *cell_of_tag, int64_t *count) {
         HIP_OK(hipMemcpy(cell_of_tag, s->cell_stage, n * sizeof(int64_t), hipMemcpyDeviceToHost));
     if (count) {
         std::vector<uint32_t> c(s->ncells);
-        HIP_OK(hipMemcpy(c.data(), s->count[(uint32_t)s->t % 3u], s->ncells * sizeof(uint32_t),
+        HIP_OK(hipMemcpy(c.data(), s->count[count_index((uint32_t)s->t, 0u)], s->ncells * sizeof(uint32_t),
                          hipMemcpyDeviceToHost));
         for (int64_t g = 0; g < s->ncells; ++g) count[g] = c[g];
     }
@@ -891,7 +891,7 @@ int dpd_autotune(dpd_system *s, int trials, int *best_variant, double *best_ms) 
         bool ok = true;
         for (int k = 0; k <= trials && ok; ++k) {
             // The fused pass appends into the next state's counts: clear them.
-            HIP_OK(launch_fill_u32(s->count[(q + 1) % 3], s->ncells, 0u, s->stream));
+            HIP_OK(launch_fill_u32(s->count[count_index(q, 1u)], s->ncells, 0u, s->stream));
             HIP_OK(hipEventRecord(ev[0], s->stream));
             if (int rc = force(s, q, FORCE_FUSED)) return rc;
             HIP_OK(hipEventRecord(ev[1], s->stream));
@@ -921,7 +921,7 @@ int dpd_autotune(dpd_system *s, int trials, int *best_variant, double *best_ms) 
             best = v;
         }
     }
-    HIP_OK(launch_fill_u32(s->count[(q + 1) % 3], s->ncells, 0u, s->stream));
+    HIP_OK(launch_fill_u32(s->count[count_index(q, 1u)], s->ncells, 0u, s->stream));
     HIP_OK(hipStreamSynchronize(s->stream));
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);

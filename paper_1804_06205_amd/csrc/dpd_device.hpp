@@ -244,6 +244,13 @@ __device__ __forceinline__ int cell_coord_unit(double x, int n) {
     return c;
 }
 
+// Which of the three rotating count arrays belongs to state q + k (k = 0, 1,
+// 2): (q + k) mod 3, taken without the 32-bit wrap of q + k (2^32 is not a
+// multiple of 3).
+__host__ __device__ __forceinline__ uint32_t count_index(uint32_t q, uint32_t k) {
+    return (q % 3u + k) % 3u;
+}
+
 __device__ __forceinline__ int64_t cell_linear(int cx, int cy, int cz, const int nc[3]) {
     return ((int64_t)cz * nc[1] + cy) * nc[0] + cx;
 }

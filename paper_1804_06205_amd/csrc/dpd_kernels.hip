@@ -140,10 +140,10 @@ __device__ __forceinline__ int xcd_brick(int bid, int nb) {
     return x * per + min(x, rem) + k;
 }
 
-// Integrate-1 (Fig. 1 steps 1-2) of one particle and its append to the
-// layout of the next state.  Shared by begin and fused so both round alike.
+// Integrate-1 (Fig. 1 steps 1-2) of one particle of state q and its append
+// to the layout of state q + 1.  Shared by begin and fused so both round alike.
 template <typename T>
-__device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, double x,
+__device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t q, double x,
                                               double y, double z, T vx, T vy, T vz, T fx,
                                               T fy, T fz, uint32_t tag, uint32_t type,
                                               bool bonded) {
@@ -167,13 +167,13 @@ __device__ __forceinline__ void drift_and_bin(const DevSys<T> &D, uint32_t qn, d
     const int cy = unit ? cell_coord_unit(y, D.nc[1]) : cell_coord(y, D.h[1], D.nc[1]);
     const int cz = unit ? cell_coord_unit(z, D.nc[2]) : cell_coord(z, D.h[2], D.nc[2]);
     const int64_t g = cell_linear(cx, cy, cz, D.nc);
-    const uint32_t k = atomicAdd(&D.count[qn % 3u][g], 1u);
+    const uint32_t k = atomicAdd(&D.count[count_index(q, 1u)][g], 1u);
     if (k >= (uint32_t)D.cap) {
         atomicOr(D.err, ERR_CELL_OVERFLOW);
         return;
     }
     const int64_t slot = g * D.cap + k;
-    const uint32_t ln = qn & 1u;
+    const uint32_t ln = (q + 1u) & 1u;
     PRec<T> p;
     p.ox = unit ? Geo<T>::encode_unit(x, cx) : Geo<T>::encode(x, cx, D.h[0]);
     p.oy = unit ? Geo<T>::encode_unit(y, cy) : Geo<T>::encode(y, cy, D.h[1]);
@@ -365,7 +365,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
 
     const int tid = threadIdx.x;
     const uint32_t lay = q & 1u;
-    const uint32_t *cnt = D.count[q % 3u];
+    const uint32_t *cnt = D.count[count_index(q, 0u)];
     const int cap = D.cap;
 
     // The sticky error word is read with the halo counts (no round trip of
@@ -399,7 +399,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     for (int i = tid; i < D.ntypes * D.ntypes; i += NT) s_a[i] = D.a[i];
     if (MODE == MODE_FUSED) {
         // Counts of state q+2 were last read for state q-1; clear this brick's.
-        uint32_t *cz2 = D.count[(q + 2u) % 3u];
+        uint32_t *cz2 = D.count[count_index(q, 2u)];
         for (int oc = tid; oc < NOC; oc += NT) {
             const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
             if (ox < ex && oy < ey && oz < ez)
@@ -840,7 +840,7 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             sp->fy = fy;
             sp->fz = fz;
         } else {
-            drift_and_bin<T>(D, q + 1u, si.x, si.y, si.z, vx, vy, vz, fx, fy, fz, pi.tag, pi.type,
+            drift_and_bin<T>(D, q, si.x, si.y, si.z, vx, vy, vz, fx, fy, fz, pi.tag, pi.type,
                              nbond > 0);
         }
     }
@@ -864,15 +864,15 @@ template <typename T>
 __device__ __forceinline__ void begin_cell(const DevSys<T> &D, uint32_t q, int64_t g) {
     if (g >= D.ncells) return;
     const uint32_t lay = q & 1u;
-    D.count[(q + 2u) % 3u][g] = 0u;
-    const uint32_t n = min(D.count[q % 3u][g], (uint32_t)D.cap);
+    D.count[count_index(q, 2u)][g] = 0u;
+    const uint32_t n = min(D.count[count_index(q, 0u)][g], (uint32_t)D.cap);
     for (uint32_t k = 0; k < n; ++k) {
         const int64_t slot = g * D.cap + k;
         const SRec<T> s = D.S[lay][slot];
         const PRec<T> p = D.P[lay][slot];
         const bool bonded = D.bond_off && D.bond_off[p.tag + 1] > D.bond_off[p.tag];
-        drift_and_bin<T>(D, q + 1u, s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz, p.tag,
-                         p.type, bonded);
+        drift_and_bin<T>(D, q, s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz, p.tag, p.type,
+                         bonded);
     }
 }
 
@@ -940,7 +940,7 @@ __global__ __launch_bounds__(256) void k_load(DevSys<T> D, uint32_t q, const dou
     const int cy = cell_coord(py, D.h[1], D.nc[1]);
     const int cz = cell_coord(pz, D.h[2], D.nc[2]);
     const int64_t g = cell_linear(cx, cy, cz, D.nc);
-    const uint32_t k = atomicAdd(&D.count[q % 3u][g], 1u);
+    const uint32_t k = atomicAdd(&D.count[count_index(q, 0u)][g], 1u);
     if (k >= (uint32_t)D.cap) {
         atomicOr(D.err, ERR_CELL_OVERFLOW);
         return;
@@ -1002,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_slotmap(DevSys<T> D, uint32_t q) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= D.ncells) return;
     const uint32_t lay = q & 1u;
-    const uint32_t n = min(D.count[q % 3u][g], (uint32_t)D.cap);
+    const uint32_t n = min(D.count[count_index(q, 0u)][g], (uint32_t)D.cap);
     for (uint32_t k = 0; k < n; ++k) {
         const int64_t slot = g * D.cap + k;
         const uint32_t tag = D.P[lay][slot].tag;
