@@ -222,6 +222,23 @@ int dpd_autotune(dpd_system *sys, int trials, int *best_variant, double *best_ms
 int dpd_pair_noise(uint64_t seed, int64_t m, const uint32_t *tag_i, const uint32_t *tag_j,
                    const uint32_t *s, int precision, double *theta);
 
+/*
+ * dpd_pair_noise for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernel and results (bit for bit), with the triples and results
+ * staged in a fixed library-owned device array instead of memory allocated
+ * per call.  No hipMalloc, hipFree or other allocating call.
+ *   m          0 .. 262144 (2^18) triples, else DPD_EINVAL; other arguments and
+ *              errors as dpd_pair_noise.  Synchronous.
+ * The array (5 MiB per device: 2^18 x (3 u32 + 1 double)) is held by every
+ * device the library runs on until the process ends and is shared by all
+ * calls on that device: calls that overlap on one device (from several
+ * threads) race, and must be serialised by the caller.
+ */
+int dpd_pair_noise_noalloc(uint64_t seed, int64_t m, const uint32_t *tag_i,
+                           const uint32_t *tag_j, const uint32_t *s, int precision,
+                           double *theta);
+
 /* Frees the system once its stream is idle; its device memory is kept for
  * later systems (see Memory above).  NULL is ignored.  A system still resident
  * in a batch is retired from it first. */

@@ -964,6 +964,74 @@ int dpd_pair_noise(uint64_t seed, int64_t m, const uint32_t *ti, const uint32_t 
     return rc;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// dpd_pair_noise without allocation: the triples and the results are staged
+// in `scratch`, a fixed device array (each device holds its own copy for the
+// life of the process).  Host code must never pass the array's name to a
+// kernel or a copy: it stands for a host-side symbol; the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+// Layout: tag_i, tag_j, s (u32, NOISE_NA_MAX each), then theta (FP64).
+// Nothing in it needs clearing: a call writes every element it reads.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t NOISE_NA_MAX = (int64_t)1 << 18;
+constexpr size_t NOISE_NA_BYTES = (size_t)NOISE_NA_MAX * (3 * sizeof(uint32_t) + sizeof(double));
+constexpr int NOISE_NA_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOISE_NA_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[NOISE_NA_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up at the first
+// call on that device).
+int scratch_on_current_device(unsigned char **out) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOISE_NA_DEVICES)
+        return fail(DPD_EDEVICE, "device %d beyond the %d the library keeps scratch for", dev,
+                    NOISE_NA_DEVICES);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(DPD_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DPD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dpd_pair_noise_noalloc(uint64_t seed, int64_t m, const uint32_t *ti, const uint32_t *tj,
+                           const uint32_t *sv, int precision, double *theta) {
+    if (m < 0 || (m > 0 && (!ti || !tj || !sv || !theta))) return fail(DPD_EINVAL, "bad arrays");
+    if (precision != DPD_PREC_FP64 && precision != DPD_PREC_MIXED)
+        return fail(DPD_EINVAL, "unknown precision %d", precision);
+    if (m > NOISE_NA_MAX)
+        return fail(DPD_EINVAL, "%lld triples exceed the %lld this call can stage",
+                    (long long)m, (long long)NOISE_NA_MAX);
+    if (m == 0) return DPD_OK;
+    unsigned char *base = nullptr;
+    if (int rc = scratch_on_current_device(&base)) return rc;
+    uint32_t *d = (uint32_t *)base;
+    double *o = (double *)(base + 3 * NOISE_NA_MAX * sizeof(uint32_t));
+    HIP_OK(hipMemcpy(d, ti, m * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d + NOISE_NA_MAX, tj, m * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d + 2 * NOISE_NA_MAX, sv, m * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_OK(launch_noise(precision == DPD_PREC_FP64, seed, m, d, d + NOISE_NA_MAX,
+                        d + 2 * NOISE_NA_MAX, o, nullptr));
+    // The copy back on the null stream follows the kernel.
+    HIP_OK(hipMemcpy(theta, o, m * sizeof(double), hipMemcpyDeviceToHost));
+    return DPD_OK;
+}
+
 int dpd_info(dpd_system *s, int64_t out[8]) {
     if (!s || !out) return fail(DPD_EINVAL, "null argument");
     out[0] = s->n;

@@ -79,6 +79,10 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, _d]),
+    "dpd_pair_noise_noalloc": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64,
+                                              ctypes.POINTER(ctypes.c_uint32),
+                                              ctypes.POINTER(ctypes.c_uint32),
+                                              ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, _d]),
     "dpd_footprint_bytes": (ctypes.c_int, [_d, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                            ctypes.c_int, _i64]),
     "dpd_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int64, ctypes.c_int, _vp,
@@ -133,6 +137,20 @@ def pair_noise(seed: int, ti, tj, s, precision: str = "mixed") -> np.ndarray:
     _check(lib().dpd_pair_noise(seed, ti.shape[0], _p(ti, u32), _p(tj, u32), _p(s, u32),
                                 PREC_FP64 if precision == "fp64" else PREC_MIXED,
                                 _p(out, _d)))
+    return out
+
+
+def pair_noise_noalloc(seed: int, ti, tj, s, precision: str = "mixed") -> np.ndarray:
+    """pair_noise through the entry point that allocates no device memory
+    (at most 2^18 triples per call)."""
+    u32 = ctypes.POINTER(ctypes.c_uint32)
+    ti = np.ascontiguousarray(ti, np.uint32)
+    tj = np.ascontiguousarray(tj, np.uint32)
+    s = np.ascontiguousarray(np.broadcast_to(s, ti.shape), np.uint32)
+    out = np.zeros(ti.shape[0])
+    _check(lib().dpd_pair_noise_noalloc(seed, ti.shape[0], _p(ti, u32), _p(tj, u32), _p(s, u32),
+                                        PREC_FP64 if precision == "fp64" else PREC_MIXED,
+                                        _p(out, _d)))
     return out
 
 
