@@ -382,6 +382,11 @@ def configs(args):
 
 def main():
     args = parse()
+    # The brick variant the autotuner picks is kept per class of system
+    # (the library's DPD_TUNE_CACHE); a repeated run on a machine reuses it.
+    os.environ.setdefault("DPD_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "dpd_tune.json"))
+    os.makedirs(os.path.dirname(os.environ["DPD_TUNE_CACHE"]), exist_ok=True)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described, not built)", file=sys.stderr)

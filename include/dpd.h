@@ -205,7 +205,14 @@ int dpd_info(dpd_system *sys, int64_t out[8]);
  *       returns it with its mean time in ms.  The state is left unchanged
  *       (the trials write only the scratch layout of the next state).
  *       Synchronises.  Variants whose tile cannot hold the densest brick are
- *       skipped.
+ *       skipped.  With the environment variable DPD_TUNE_CACHE naming a file,
+ *       the choice is stored there per class of system (device architecture,
+ *       precision, particle types, power-of-two class of the cell count,
+ *       particles per cell, cubic or not, variant table), and a later call for
+ *       a system of the same class, in any process, takes the stored variant
+ *       and time without timing anything.
+ * The variants differ in brick shape and in threads per brick: variants 5 and
+ * 6 give each thread about two particles of the brick.
  */
 int dpd_variant_count(void);
 int dpd_variant_shape(int variant, int out[5]);

@@ -1,11 +1,13 @@
 // C ABI of the DPD step library (include/dpd.h): system lifetime, parameter
 // and bond upload, the step schedule, state and observable read-back.
 #include <hip/hip_runtime.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -506,6 +508,79 @@ int check_usable(dpd_system *s) {
     return DPD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner cache.  With DPD_TUNE_CACHE naming a file, dpd_autotune keeps the
+// brick variant it picked for each class of system there (a JSON object, one
+// entry per line, rewritten through a temporary file and a rename), and a
+// later call for the same class, in this process or another, takes the entry
+// without timing anything.  The class: device architecture, precision,
+// number of particle types, cell count (power-of-two size class), particles
+// per cell (rounded), cubic or non-cubic cells, and a hash of the variant
+// table, so entries of another table are not reused.
+// ---------------------------------------------------------------------------
+std::string tune_key(const dpd_system *s) {
+    std::string arch = "unknown";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, s->dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch.resize(c);
+    }
+    int lg = 0;
+    while (((int64_t)1 << (lg + 1)) <= s->ncells) ++lg;
+    const long dens = std::lround((double)s->n / (double)s->ncells);
+    uint32_t h = 2166136261u;       // FNV-1a over the variant shapes
+    for (int v = 0; v < force_variant_count(); ++v) {
+        int sh[5];
+        force_variant_shape(v, sh);
+        for (int k = 0; k < 5; ++k) {
+            h ^= (uint32_t)sh[k];
+            h *= 16777619u;
+        }
+    }
+    const bool cubic = s->h[0] == s->h[1] && s->h[0] == s->h[2];
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|%s|types%d|cells2^%d|rho%ld|%s|table%08x", arch.c_str(),
+                  s->prec == DPD_PREC_FP64 ? "fp64" : "mixed", s->ntypes, lg, dens,
+                  cubic ? "cubic" : "noncubic", h);
+    return buf;
+}
+
+// Entries of a cache file: key -> (variant, ms).  Lines that are not entries
+// ("{", "}") or do not parse are skipped.
+std::map<std::string, std::pair<int, double>> tune_read(const char *path) {
+    std::map<std::string, std::pair<int, double>> m;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return m;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        const char *q1 = std::strchr(line, '"');
+        if (!q1) continue;
+        const char *q2 = std::strchr(q1 + 1, '"');
+        if (!q2) continue;
+        int v = -1;
+        double ms = 0.0;
+        if (std::sscanf(q2 + 1, ": {\"variant\": %d, \"ms\": %lf", &v, &ms) == 2)
+            m[std::string(q1 + 1, q2)] = {v, ms};
+    }
+    std::fclose(f);
+    return m;
+}
+
+void tune_write(const char *path, const std::map<std::string, std::pair<int, double>> &m) {
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto &e : m)
+        std::fprintf(f, "\"%s\": {\"variant\": %d, \"ms\": %.17g}%s\n", e.first.c_str(),
+                     e.second.first, e.second.second, ++k < m.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
+}
+
 int batch_detach(dpd_batch *b, int slot);
 
 }  // namespace
@@ -875,6 +950,20 @@ int dpd_set_variant(dpd_system *s, int variant) {
 int dpd_autotune(dpd_system *s, int trials, int *best_variant, double *best_ms) {
     if (int rc = check_usable(s)) return rc;
     if (trials < 1) return fail(DPD_EINVAL, "trials must be >= 1");
+    const char *cache = std::getenv("DPD_TUNE_CACHE");
+    std::string key;
+    if (cache && *cache) {
+        key = tune_key(s);
+        const auto m = tune_read(cache);
+        const auto it = m.find(key);
+        if (it != m.end() && it->second.first >= 0 &&
+            it->second.first < force_variant_count()) {
+            s->variant = it->second.first;
+            if (best_variant) *best_variant = it->second.first;
+            if (best_ms) *best_ms = it->second.second;
+            return DPD_OK;
+        }
+    }
     if (int rc = freeze(s)) return rc;
     if (int rc = ensure_force(s)) return rc;
     if (int rc = check_device(s)) return rc;
@@ -932,6 +1021,12 @@ int dpd_autotune(dpd_system *s, int trials, int *best_variant, double *best_ms) 
     s->variant = best;
     if (best_variant) *best_variant = best;
     if (best_ms) *best_ms = best_t;
+    if (!key.empty()) {
+        // A failed write leaves the choice in force for this system only.
+        auto m = tune_read(cache);
+        m[key] = {best, best_t};
+        tune_write(cache, m);
+    }
     return DPD_OK;
 }
 

@@ -1109,13 +1109,18 @@ static hipError_t launch_force_v(const DevSys<T> &D, uint32_t q, int mode, hipSt
 
 // Brick variants, selected by index: {BX, BY, BZ, threads, LDS capacity}.  The
 // capacity sits ~5 standard deviations above a rho = 3 neighbourhood's mean;
-// denser neighbourhoods are processed in chunks.
+// denser neighbourhoods are processed in chunks.  Variants 5 and 6 take a
+// brick with half the threads (about two particles per thread, in two passes
+// over the staged neighbourhood): smaller work-groups for small boxes.
 #define DPD_VARIANTS(X)                                                                   \
     X(0, 4, 4, 4, 256, 800)                                                               \
     X(1, 5, 4, 4, 256, 896)                                                               \
     X(2, 5, 5, 4, 320, 1056)                                                              \
     X(3, 4, 4, 2, 128, 540)                                                               \
-    X(4, 2, 2, 2, 64, 256)
+    X(4, 2, 2, 2, 64, 256)                                                                \
+    X(5, 5, 4, 4, 128, 896)                                                               \
+    X(6, 4, 4, 4, 128, 800)
+constexpr int NVARIANTS = 7;
 
 template <typename T>
 hipError_t launch_force(const DevSys<T> &D, uint32_t q, int mode, int variant, hipStream_t st) {
@@ -1128,10 +1133,10 @@ hipError_t launch_force(const DevSys<T> &D, uint32_t q, int mode, int variant, h
     }
 }
 
-int force_variant_count() { return 5; }
+int force_variant_count() { return NVARIANTS; }
 
 void force_variant_shape(int variant, int out[5]) {
-    static const int t[5][5] = {
+    static const int t[NVARIANTS][5] = {
 #define DPD_ROW(i, bx, by, bz, nt, hc) {bx, by, bz, nt, hc},
         DPD_VARIANTS(DPD_ROW)
 #undef DPD_ROW
