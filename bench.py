@@ -216,10 +216,14 @@ def replica_stream(args):
     print(json.dumps(line), flush=True)
 
 
-# CAMUS times from the paper's Table 1 (ms per step, 2x Xeon E5-2640, rho = 3,
-# a = 25): one thread, and the best thread count with that count.
+# CAMUS times from the paper's performance section (ms per step, 2x Xeon
+# E5-2640, rho = 3, a = 25): one thread, and the best thread count with that
+# count.  Table 1: the fluid; Table 3: the same boxes with the alpha-helix
+# model's 1-3 and 1-5 terms.
 PAPER_TABLE1 = {5000: (10.1, 2.8, 12), 10000: (20.5, 5.1, 16), 50000: (99.0, 24.8, 12),
                 100000: (194.5, 48.7, 8)}
+PAPER_TABLE3 = {5000: (10.2, 2.8, 12), 10000: (20.8, 5.2, 8), 50000: (104.9, 25.9, 8),
+                100000: (194.7, 49.4, 8)}
 
 
 def cpu_baseline_ms(w, nthreads, gomp):
@@ -250,12 +254,13 @@ def _gpu_ms_per_step(g, steps, stream):
 
 
 def paper_sweep(args):
-    """The paper's benchmark boxes (single-species fluid, rho = 3, a = 25,
-    N = 5k..100k): GPU ms/step through dpd_step and through a one-replica batch
-    (graph-captured windows), and the oracle at one and at all host threads,
-    with the paper's CAMUS times beside them.  Acc = 100 T1 / T and
-    Par = Acc / threads as in the paper's Eqs. 9-10, T1 = the oracle on one
-    thread."""
+    """The paper's benchmark boxes (rho = 3, a = 25, N = 5k..100k), each as the
+    plain fluid (Table 1) and with ceil(0.03 N / 60) chains of the alpha-helix
+    deck's bonds (Table 3): GPU ms/step through dpd_step and through a
+    one-replica batch (graph-captured windows), and the oracle at one and at
+    all host threads, with the paper's CAMUS times beside them.
+    Acc = 100 T1 / T and Par = Acc / threads as in the paper's Eqs. 9-10,
+    T1 = the oracle on one thread."""
     import ctypes
     import torch
     import oracle
@@ -268,44 +273,46 @@ def paper_sweep(args):
     stream = torch.cuda.Stream()
     rows = []
     for N in sorted(PAPER_TABLE1):
-        L = (N / 3.0) ** (1.0 / 3.0)
-        w = W.fluid(L, seed=11, name=f"fluid_N{N}")
-        g = dpd.System.from_workload(w, stream=stream)
-        g.step(args.warmup)
-        g.sync()
-        variant, _ = g.autotune(3)
-        ms = _gpu_ms_per_step(g, args.steps, stream)
-        g.close()
-        # One replica through the batch path: K-step windows replayed as a graph.
-        K = 100
-        g = dpd.System.from_workload(w)
-        with dpd.Batch(1 << 40, 1, variant=variant) as b:
-            b.admit(g, 10 ** 7)
-            b.advance(K)
-            b.poll()
-            t0 = time.perf_counter()
-            nwin = max(1, args.steps // K)
-            for _ in range(nwin):
+        for chains in (False, True):
+            w = W.sweep_box(N, chains=chains)
+            g = dpd.System.from_workload(w, stream=stream)
+            g.step(args.warmup)
+            g.sync()
+            variant, _ = g.autotune(3)
+            ms = _gpu_ms_per_step(g, args.steps, stream)
+            g.close()
+            # One replica through the batch path: K-step windows replayed as a graph.
+            K = 100
+            g = dpd.System.from_workload(w)
+            with dpd.Batch(1 << 40, 1, variant=variant) as b:
+                b.admit(g, 10 ** 7)
                 b.advance(K)
-            b.poll()
-            ms_graph = (time.perf_counter() - t0) * 1e3 / (nwin * K)
-        g.close()
-        t_or = {nt: cpu_baseline_ms(w, nt, gomp) for nt in (1, nthreads)}
-        gomp.omp_set_num_threads(nthreads)
-        p1, pbest, pth = PAPER_TABLE1[N]
-        best = min(ms, ms_graph)
-        rows.append({"N": N, "L": L, "brick": list(dpd.variants()[variant][:3]),
-                     "gpu_ms_per_step": ms, "gpu_graph_ms_per_step": ms_graph,
-                     "gpu_particle_steps_per_s": N / best * 1e3,
-                     "oracle_ms_1thread": t_or[1], "oracle_ms_all": t_or[nthreads],
-                     "oracle_threads": nthreads,
-                     "acc_gpu": 100.0 * t_or[1] / best,
-                     "acc_oracle": 100.0 * t_or[1] / t_or[nthreads],
-                     "par_oracle": 100.0 * t_or[1] / t_or[nthreads] / nthreads,
-                     "paper_camus_ms_1thread": p1, "paper_camus_ms_best": pbest,
-                     "paper_camus_best_threads": pth})
-        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
-    top = rows[-1]
+                b.poll()
+                t0 = time.perf_counter()
+                nwin = max(1, args.steps // K)
+                for _ in range(nwin):
+                    b.advance(K)
+                b.poll()
+                ms_graph = (time.perf_counter() - t0) * 1e3 / (nwin * K)
+            g.close()
+            t_or = {nt: cpu_baseline_ms(w, nt, gomp) for nt in (1, nthreads)}
+            gomp.omp_set_num_threads(nthreads)
+            p1, pbest, pth = (PAPER_TABLE3 if chains else PAPER_TABLE1)[N]
+            best = min(ms, ms_graph)
+            rows.append({"N": N, "L": w.L[0], "table": 3 if chains else 1,
+                         "chains": int(w.types.sum() // 60), "bonds": w.nbonds, "dt": w.dt,
+                         "brick": list(dpd.variants()[variant][:3]),
+                         "gpu_ms_per_step": ms, "gpu_graph_ms_per_step": ms_graph,
+                         "gpu_particle_steps_per_s": N / best * 1e3,
+                         "oracle_ms_1thread": t_or[1], "oracle_ms_all": t_or[nthreads],
+                         "oracle_threads": nthreads,
+                         "acc_gpu": 100.0 * t_or[1] / best,
+                         "acc_oracle": 100.0 * t_or[1] / t_or[nthreads],
+                         "par_oracle": 100.0 * t_or[1] / t_or[nthreads] / nthreads,
+                         "paper_camus_ms_1thread": p1, "paper_camus_ms_best": pbest,
+                         "paper_camus_best_threads": pth})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    top = [r for r in rows if r["table"] == 1][-1]
     line = {"metric": "particle-steps/s (paper box sizes, rho=3)",
             "value": top["gpu_particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup,
@@ -313,7 +320,7 @@ def paper_sweep(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "paper_sweep", "N": sorted(PAPER_TABLE1), "rho": 3, "a": 25.0,
-                       "gamma": 4.5, "sigma": 3.0, "dt": 0.04,
+                       "gamma": 4.5, "sigma": 3.0, "dt": [0.04, 0.02],
                        "precision": "FP32 forces/velocities, FP64 positions"},
             "sweep": rows, "roofline": None}
     print(json.dumps(line), flush=True)

@@ -259,16 +259,55 @@ def helix(L: float = 20.0, rho: float = 3.0, seed: int = 6, beads: int = 60,
     vel = _velocities(rng, n, 1.0)
     types = np.zeros(n, np.uint8)
     types[:beads] = 1
-    rec = [(BOND_HARMONIC, i, i + 1, 0.6, 160.0, 0.0) for i in range(beads - 1)]
-    rec += [(BOND_HARMONIC, i, i + 2, 1.2, 80.0, 0.0) for i in range(beads - 2)]
-    rec += [(BOND_MORSE_PAPER, i, i + 2, 0.9, 12.0, 8.0) for i in range(beads - 2)]
-    rec += [(BOND_MORSE_PAPER, i, i + 4, 0.6, 12.0, 8.0) for i in range(beads - 4)]
-    bt, bi, bj, re, kk, al = _bond_arrays(rec)
+    bt, bi, bj, re, kk, al = _bond_arrays(helix_records(0, beads))
     gamma = 4.2
     return Workload(name="helix_L20", L=(L, L, L), pos=pos, vel=vel, types=types,
                     ntypes=2, a=np.array([[50.0, 55.0], [55.0, 50.0]]), gamma=gamma,
                     sigma=math.sqrt(2.0 * gamma * 1.0), dt=0.02, seed=seed,
                     steps=10000, btype=bt, bi=bi, bj=bj, r_e=re, k=kk, alpha=al, **kw)
+
+
+def helix_records(offset: int, beads: int):
+    """The bond records of one chain of the alpha-helix deck (Fig. 3b) starting
+    at tag `offset`: 1-2 harmonic (C=160, r_e=0.6), 1-3 harmonic (C=80,
+    r_e=1.2), 1-3 modified Morse (K_M=12, alpha=8, r_e=0.9), 1-5 modified Morse
+    (K_M=12, alpha=8, r_e=0.6)."""
+    o = offset
+    rec = [(BOND_HARMONIC, o + i, o + i + 1, 0.6, 160.0, 0.0) for i in range(beads - 1)]
+    rec += [(BOND_HARMONIC, o + i, o + i + 2, 1.2, 80.0, 0.0) for i in range(beads - 2)]
+    rec += [(BOND_MORSE_PAPER, o + i, o + i + 2, 0.9, 12.0, 8.0) for i in range(beads - 2)]
+    rec += [(BOND_MORSE_PAPER, o + i, o + i + 4, 0.6, 12.0, 8.0) for i in range(beads - 4)]
+    return rec
+
+
+def sweep_box(N: int, chains: bool = False, seed: int = 11, beads: int = 60,
+              fraction: float = 0.03) -> Workload:
+    """A box of the paper's benchmark sweep (performance section, Tables 1-3):
+    N beads at rho = 3 in a cubic box of edge (N/3)^(1/3), a = 25, gamma = 4.5,
+    sigma = 3.  With chains (Table 3), ceil(fraction N / beads) chains of the
+    alpha-helix deck's bonds (60 beads, Fig. 3b records, b = 0.6 random walk)
+    replace solvent beads; every pair keeps a = 25, so the pair work equals
+    Table 1's, and dt = 0.02 (the deck's step; its Morse terms need it)."""
+    L = (N / 3.0) ** (1.0 / 3.0)
+    if not chains:
+        return fluid(L, seed=seed, name=f"sweep_N{N}")
+    Lv = _box(L)
+    n = int(round(3.0 * L ** 3))
+    nchains = int(math.ceil(fraction * n / beads))
+    rng = _rng(seed)
+    chain = _walk(rng, nchains, beads, 0.6, Lv)
+    solvent = _into_box(rng.uniform(0.0, 1.0, size=(n - nchains * beads, 3)) * Lv, Lv)
+    pos = np.concatenate([chain, solvent])
+    vel = _velocities(rng, n, 1.0)
+    types = np.zeros(n, np.uint8)
+    types[:nchains * beads] = 1
+    rec = []
+    for c in range(nchains):
+        rec += helix_records(c * beads, beads)
+    bt, bi, bj, re, kk, al = _bond_arrays(rec)
+    return Workload(name=f"sweep_N{N}_chains", L=tuple(float(v) for v in Lv), pos=pos,
+                    vel=vel, types=types, ntypes=2, a=np.full((2, 2), 25.0), dt=0.02,
+                    seed=seed, btype=bt, bi=bi, bj=bj, r_e=re, k=kk, alpha=al)
 
 
 # The five benchmark workloads by name.

@@ -365,6 +365,34 @@ def test_full_size_bonded_configurations(cfg):
     assert t == 10 and dx <= TOL_X10["mixed"] and dv <= 1e-2
 
 
+@pytest.mark.parametrize("chains", [False, True])
+def test_paper_sweep_box(chains):
+    # The paper's N = 50 000 benchmark box (L = 25.54: 25 cells of edge
+    # 1.0217 per axis, so the integer brick frame with non-unit cells), as the
+    # plain fluid (Table 1) and with the Table 3 chains (25 chains of the
+    # alpha-helix deck's 1-2 / 1-3 harmonic and 1-3 / 1-5 modified Morse
+    # records, dt = 0.02): forces of the initial state, then ten steps, and
+    # the cell list the last step built.
+    w = W.sweep_box(50000, chains=chains)
+    assert abs(w.L[0] - 25.544) < 1e-3 and w.n == 50000
+    fo = _oracle_force(w, 0)
+    with dpd.System.from_workload(w) as g:
+        assert g.info()["nx"] == 25
+        g.set_state(w.pos, w.vel, None, 0)
+        _, _, fg, _ = g.get_state()
+        g.step(10)
+        xg, vg, _, t = g.get_state()
+        _cells_vs_oracle(g, xg, w.L)
+    err = np.abs(fg - fo).max()
+    st = oracle.State.from_workload(w)
+    st.step(10)
+    dx = np.abs(_min_image_diff(xg, st.pos, w.L)).max()
+    print(f"sweep N=50000 chains={chains}: force max-abs {err:.3e}; 10 steps pos {dx:.3e}",
+          flush=True)
+    assert err <= TOL_F["mixed"]
+    assert t == 10 and dx <= TOL_X10["mixed"]
+
+
 def test_coincident_particles():
     # Two particles exactly on top of each other: no force between them (e is
     # undefined; Eq. 4 needs r > 0), the rest as the oracle has it; the pair
