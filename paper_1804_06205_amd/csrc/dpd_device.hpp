@@ -259,27 +259,43 @@ __device__ __forceinline__ double min_image(double d, double L) {
     return d - L * rint(d / L);
 }
 
+// 1 / sqrt(a) for a > 0: the hardware estimate refined by two Newton steps,
+// y <- y + y (1 - a y^2) / 2 (each doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-a * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 // ---------------------------------------------------------------------------
-// Bond term (Eqs. 6-8, Fig. 3a).  d = x_i - x_j (minimum image).  Returns
-// the coefficient c with F_i = c d; energy and virial through u, w.
+// Bond term (Eqs. 6-8, Fig. 3a), in FP64.  d = x_i - x_j (minimum image),
+// r2 = |d|^2.  Returns the coefficient c with F_i = c d; energy and virial
+// through u, w.  Type 1 harmonic, C (r - r_e)^2 / 2 (r_e = 0: a spring of
+// rest length zero, F = -C d); type 2 the paper's modified Morse,
+// K (1 - e^{-alpha |r - r_e|})^2; type 3 the standard Morse, K ((1 -
+// e^{-alpha (r - r_e)})^2 - 1).  A bond at r = 0 exerts no force except the
+// zero-length spring.  One reciprocal square root serves every type and the
+// two Morse forms share one exponential, so a wave whose lanes hold
+// different types runs one short path and one exponential.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T bond_coef(int type, T r2, T r_e, T k, T alpha, T &u, T &w) {
-    const T r = t_sqrt(r2);
-    T c = (T)0;
+__device__ __forceinline__ double bond_coef(int type, double r2, double r_e, double k,
+                                            double alpha, double &u, double &w) {
+    const double rinv = r2 > 0.0 ? rsqrt_nr(r2) : 0.0;
+    const double r = r2 * rinv;
+    const double x = r - r_e;
+    double c;
     if (type == 1) {
-        const T x = r - r_e;
-        if (r_e == (T)0) c = -k;
-        else if (r > (T)0) c = -k * x / r;
-        u = (T)0.5 * k * x * x;
-    } else if (type == 2) {
-        const T E = t_exp(-alpha * t_abs(r - r_e));
-        if (r > (T)0) c = (T)-2 * alpha * k * E * ((T)1 - E) / r;
-        u = k * ((T)1 - E) * ((T)1 - E);
+        c = r_e == 0.0 ? -k : -k * x * rinv;
+        u = 0.5 * k * x * x;
     } else {
-        const T E = t_exp(-alpha * (r - r_e));
-        if (r > (T)0) c = (T)-2 * alpha * k * E * ((T)1 - E) / r;
-        u = k * (((T)1 - E) * ((T)1 - E) - (T)1);
+        const double E = exp(-alpha * (type == 2 ? fabs(x) : x));
+        const double omE = 1.0 - E;
+        c = -2.0 * alpha * k * E * omE * rinv;
+        u = k * (omE * omE - (type == 2 ? 0.0 : 1.0));
     }
     w = c * r2;
     return c;

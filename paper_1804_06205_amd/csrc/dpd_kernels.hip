@@ -242,87 +242,73 @@ template <typename T, typename AT, int HCAP> struct Tile {
 };
 
 // Copies halo cells [c0, c1) into the tile at their offsets relative to cell
-// c0, one thread per cell, each record straight to its place in ascending tag
-// order: its rank among the cell's tags (distinct).
+// c0 in ascending tag order inside every cell.  One thread per record: every
+// record of the chunk is loaded at once (one memory round trip, however full
+// the densest cell), its tag is parked in the tile's vx array, each record is
+// ranked among its cell's tags (distinct) from there, and after a barrier it
+// is stored at its rank.  All threads of the block must call it.
 template <typename T, int HX, int HY, int NT, bool IGEO, typename AT, int HCAP>
 __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, int c0x, int c0y,
                                             int c0z, const int *s_hstart, int c0, int c1,
                                             const Tile<T, AT, HCAP> &tl) {
+    constexpr int RPT = (HCAP + NT - 1) / NT;   // records per thread, at most
     const int cap = D.cap;
     const int off0 = s_hstart[c0];
-    for (int hc = c0 + (int)threadIdx.x; hc < c1; hc += NT) {
-        const int lo = s_hstart[hc] - off0, n = s_hstart[hc + 1] - s_hstart[hc];
-        if (n == 0) continue;
-        const PRec<T> *src = D.P[lay] + halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc) * cap;
-        const uint32_t hx = (uint32_t)(hc % HX), hy = (uint32_t)((hc / HX) % HY),
-                       hz = (uint32_t)(hc / (HX * HY));
-        auto put = [&](const PRec<T> &r, int rank) __attribute__((always_inline)) {
-            AT a;
-            if constexpr (IGEO) {
-                a.qx = (uint32_t)r.ox + (hx << 29);
-                a.qy = (uint32_t)r.oy + (hy << 29);
-                a.qz = (uint32_t)r.oz + (hz << 29);
-            } else {
-                a.ox = r.ox;
-                a.oy = r.oy;
-                a.oz = r.oz;
-            }
-            a.tag = r.tag;
-            const int j = lo + rank;
-            tl.A[j] = a;
-            tl.vx[j] = r.vx;
-            tl.vy[j] = r.vy;
-            tl.vz[j] = r.vz;
-            tl.type[j] = (uint8_t)r.type;
-        };
-        // Cells of up to 8 records (nearly every cell at rho = 3): all their
-        // tags are read at once and ranked in registers, then the records are
-        // placed four at a time, instead of rereading the tags one load at a
-        // time for each group of four.  Larger cells still do that.
-        if (n <= 8) {
-            // Ranks as eight 4-bit fields, so the tags are dead before the
-            // records are loaded.
-            uint32_t rk = 0;
-            {
-                uint32_t tg[8];
+    const int m = s_hstart[c1] - off0;           // <= HCAP (chunk planning)
+    uint32_t *park = reinterpret_cast<uint32_t *>(tl.vx);
+    PRec<T> r[RPT];
+    int hcell[RPT];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) tg[u] = u < n ? src[u].tag : 0xFFFFFFFFu;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    uint32_t c = 0;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) c += tg[k] < tg[u] ? 1u : 0u;
-                    rk |= c << (4 * u);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 8; c += 4) {
-                if (c >= n) break;
-                PRec<T> r[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (c + u < n) r[u] = src[c + u];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (c + u < n) put(r[u], (int)((rk >> (4 * (c + u))) & 0xFu));
-            }
-            continue;
+    for (int u = 0; u < RPT; ++u) {
+        const int t = (int)threadIdx.x + u * NT;
+        hcell[u] = -1;
+        if (t < m) {
+            // The cell holding chunk record t: the last cell whose start is
+            // <= t (empty cells share their successor's start).
+            const int hc = c0 + find_bin(s_hstart + c0, c1 - c0, t + off0);
+            hcell[u] = hc;
+            r[u] = D.P[lay][halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc) * cap +
+                            (t + off0 - s_hstart[hc])];
         }
-        for (int k0 = 0; k0 < n; k0 += 4) {
-            PRec<T> r[4];
+    }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (k0 + u < n) r[u] = src[k0 + u];
-            int rank[4] = {0, 0, 0, 0};
-            for (int k = 0; k < n; ++k) {
-                const uint32_t tk = src[k].tag;
+    for (int u = 0; u < RPT; ++u)
+        if (hcell[u] >= 0) park[(int)threadIdx.x + u * NT] = r[u].tag;
+    __syncthreads();
+    int rank[RPT];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) rank[u] += tk < r[u].tag ? 1 : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (k0 + u < n) put(r[u], rank[u]);
+    for (int u = 0; u < RPT; ++u) {
+        rank[u] = 0;
+        if (hcell[u] >= 0) {
+            const int lo = s_hstart[hcell[u]] - off0, hi = s_hstart[hcell[u] + 1] - off0;
+            int c = 0;
+            for (int k = lo; k < hi; ++k) c += park[k] < r[u].tag ? 1 : 0;
+            rank[u] = lo + c;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        if (hcell[u] < 0) continue;
+        const int hc = hcell[u];
+        const PRec<T> &pr = r[u];
+        AT a;
+        if constexpr (IGEO) {
+            a.qx = (uint32_t)pr.ox + ((uint32_t)(hc % HX) << 29);
+            a.qy = (uint32_t)pr.oy + ((uint32_t)((hc / HX) % HY) << 29);
+            a.qz = (uint32_t)pr.oz + ((uint32_t)(hc / (HX * HY)) << 29);
+        } else {
+            a.ox = pr.ox;
+            a.oy = pr.oy;
+            a.oz = pr.oz;
+        }
+        a.tag = pr.tag;
+        const int j = rank[u];
+        tl.A[j] = a;
+        tl.vx[j] = pr.vx;
+        tl.vy[j] = pr.vy;
+        tl.vz[j] = pr.vz;
+        tl.type[j] = (uint8_t)pr.type;
     }
 }
 
@@ -331,7 +317,7 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, in
 // each at most the compile-time extent, so no brick is a thin remainder.  fin
 // (MODE_FUSED only) ends the step in place like MODE_FINISH instead of moving
 // on to state q + 1; replicas of a batch use it for their last step of a window.
-template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO>
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO, bool BONDS>
 __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int b, int nbx,
                                             int nby, int nbz, uint64_t thr, bool fin) {
     constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
@@ -767,42 +753,136 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             }
         }
 
-        if (!have) continue;
-
         // Bonds (Eq. 8): every record owned by this particle, in input order,
         // evaluated in FP64 (stiff Morse terms reach |F| ~ 1e2, where FP32
-        // rounding alone would exceed the force tolerance).
-        const SRec<T> si = D.S[lay][slot];
+        // rounding alone would exceed the force tolerance).  Two schedules
+        // with the same sums, chosen per wave:
+        //  * few bonded lanes with several records each (chains in solvent):
+        //    the wave's records, at most 64, are dealt one per lane, and each
+        //    owner adds its terms in record order from the lanes that
+        //    evaluated them, so no lane evaluates its records one by one;
+        //  * otherwise (bonds spread over many lanes, or more than 64): each
+        //    lane runs its own records, four at a time, their partners'
+        //    slots and positions going out together.
         double oub = 0.0, owb = 0.0;
         double gbx = 0.0, gby = 0.0, gbz = 0.0;
         uint32_t nbond = 0;
-        if (D.bond_off) {
-            const uint32_t k0 = D.bond_off[pi.tag], k1 = D.bond_off[pi.tag + 1];
-            nbond = k1 - k0;
-            for (uint32_t k = k0; k < k1; ++k) {
-                const BondEnt<T> be = D.bonds[k];
-                uint32_t sj = D.slot_of_tag[lay][be.partner];
-                if ((int64_t)sj >= D.ncells * cap) {
-                    atomicOr(D.err, ERR_INDEX);
-                    sj = 0;
+        SRec<T> si{};
+        if (have) si = D.S[lay][slot];
+        if (BONDS && D.bond_off) {
+            const int lane = (int)(threadIdx.x & 63u);
+            uint32_t k0 = 0u;
+            if (have) {
+                k0 = D.bond_off[pi.tag];
+                nbond = D.bond_off[pi.tag + 1] - k0;
+            }
+            uint32_t total = nbond, mx = nbond;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                total += (uint32_t)__shfl_xor(total, d);
+                mx = max(mx, (uint32_t)__shfl_xor(mx, d));
+            }
+            if (total <= 64u && mx >= 3u) {
+                // Exclusive prefix of the record counts over the wave.
+                uint32_t incl = nbond;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t t = __shfl_up(incl, d);
+                    if (lane >= d) incl += t;
                 }
-                const SRec<T> &pj = D.S[lay][sj];
-                const double ddx = min_image(si.x - pj.x, D.L[0]);
-                const double ddy = min_image(si.y - pj.y, D.L[1]);
-                const double ddz = min_image(si.z - pj.z, D.L[2]);
-                double u, w;
-                const double c = bond_coef<double>(be.type, ddx * ddx + ddy * ddy + ddz * ddz,
-                                                   be.r_e, be.k, be.alpha, u, w);
-                gbx += c * ddx;
-                gby += c * ddy;
-                gbz += c * ddz;
-                oub += 0.5 * u;
-                owb += 0.5 * w;
+                const uint32_t pre = incl - nbond;
+                // Record g = lane belongs to the last lane o whose prefix is
+                // <= g (lanes without records share their successor's).
+                const uint32_t g = (uint32_t)lane;
+                int o = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (__shfl(pre, o + step) <= g) o += step;
+                const uint32_t kk = __shfl(k0, o) + (g - __shfl(pre, o));
+                const double ox = __shfl(si.x, o), oy = __shfl(si.y, o), oz = __shfl(si.z, o);
+                double tx = 0.0, ty = 0.0, tz = 0.0, tu = 0.0, tw = 0.0;
+                if (g < total) {
+                    const BondEnt<T> &be = D.bonds[kk];
+                    uint32_t sj = D.slot_of_tag[lay][be.partner];
+                    if ((int64_t)sj >= D.ncells * cap) {
+                        atomicOr(D.err, ERR_INDEX);
+                        sj = 0u;
+                    }
+                    const SRec<T> &pj = D.S[lay][sj];
+                    const double ddx = min_image(ox - pj.x, D.L[0]);
+                    const double ddy = min_image(oy - pj.y, D.L[1]);
+                    const double ddz = min_image(oz - pj.z, D.L[2]);
+                    double ub, wb;
+                    const double c = bond_coef(be.type, ddx * ddx + ddy * ddy + ddz * ddz,
+                                               be.r_e, be.k, be.alpha, ub, wb);
+                    tx = c * ddx;
+                    ty = c * ddy;
+                    tz = c * ddz;
+                    tu = 0.5 * ub;
+                    tw = 0.5 * wb;
+                }
+                // The owner's record j was evaluated by lane pre + j.
+                for (uint32_t j = 0; j < mx; ++j) {
+                    const int sl = (int)((pre + j) & 63u);
+                    const double vx = __shfl(tx, sl), vy = __shfl(ty, sl), vz = __shfl(tz, sl);
+                    const double vu = __shfl(tu, sl), vw = __shfl(tw, sl);
+                    if (j < nbond) {
+                        gbx += vx;
+                        gby += vy;
+                        gbz += vz;
+                        oub += vu;
+                        owb += vw;
+                    }
+                }
+            } else if (have) {
+                const uint32_t k1 = k0 + nbond;
+                for (uint32_t kb = k0; kb < k1; kb += 4u) {
+                    const uint32_t nb = min(k1 - kb, 4u);
+                    uint32_t sj[4];
+#pragma unroll
+                    for (uint32_t u = 0; u < 4u; ++u)
+                        sj[u] = u < nb ? D.bonds[kb + u].partner : 0u;
+#pragma unroll
+                    for (uint32_t u = 0; u < 4u; ++u) {
+                        if (u < nb) {
+                            sj[u] = D.slot_of_tag[lay][sj[u]];
+                            if ((int64_t)sj[u] >= D.ncells * cap) {
+                                atomicOr(D.err, ERR_INDEX);
+                                sj[u] = 0u;
+                            }
+                        }
+                    }
+                    double px[4], py[4], pz[4];
+#pragma unroll
+                    for (uint32_t u = 0; u < 4u; ++u) {
+                        const SRec<T> &pj = D.S[lay][u < nb ? sj[u] : sj[0]];
+                        px[u] = pj.x;
+                        py[u] = pj.y;
+                        pz[u] = pj.z;
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < 4u; ++u) {
+                        if (u >= nb) break;
+                        const BondEnt<T> &be = D.bonds[kb + u];
+                        const double ddx = min_image(si.x - px[u], D.L[0]);
+                        const double ddy = min_image(si.y - py[u], D.L[1]);
+                        const double ddz = min_image(si.z - pz[u], D.L[2]);
+                        double ub, wb;
+                        const double c = bond_coef(be.type, ddx * ddx + ddy * ddy + ddz * ddz,
+                                                   be.r_e, be.k, be.alpha, ub, wb);
+                        gbx += c * ddx;
+                        gby += c * ddy;
+                        gbz += c * ddz;
+                        oub += 0.5 * ub;
+                        owb += 0.5 * wb;
+                    }
+                }
             }
             fx = (T)((double)fx + gbx);
             fy = (T)((double)fy + gby);
             fz = (T)((double)fz + gbz);
         }
+        if (!have) continue;
 
         if (MODE == MODE_OBS) {
             const uint32_t tg = pi.tag;
@@ -851,11 +931,14 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
 #define DPD_WAVES_PER_EU 4
 #endif
 
-template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO>
+// BONDS = false drops the bond terms from the code (systems without bonds).
+template <typename T, int BX, int BY, int BZ, int NT, int HCAP, int MODE, bool IGEO,
+          bool BONDS = true>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(IGEO ? DPD_WAVES_PER_EU : 1)))
 void k_force(DevSys<T> D, uint32_t q, int nbx, int nby, int nbricks, uint64_t thr) {
-    force_brick<T, BX, BY, BZ, NT, HCAP, MODE, IGEO>(D, q, xcd_brick(blockIdx.x, nbricks), nbx,
-                                                     nby, nbricks / (nbx * nby), thr, false);
+    force_brick<T, BX, BY, BZ, NT, HCAP, MODE, IGEO, BONDS>(D, q, xcd_brick(blockIdx.x, nbricks),
+                                                            nbx, nby, nbricks / (nbx * nby), thr,
+                                                            false);
 }
 
 // begin: integrate-1 and binning of every particle of resting state q; one
@@ -900,9 +983,8 @@ void k_force_batch(const BatchEnt *__restrict__ tab, BatchDev B, uint32_t k, uin
     if (tgt - t0 <= k) return;     // the replica reached its target earlier
     const uint32_t q = t0 + k + 1u;
     const BatchEnt &E = tab[w.slot];
-    force_brick<float, BX, BY, BZ, NT, HCAP, MODE_FUSED, true>(E.D, q, (int)w.item, E.nbx, E.nby,
-                                                               E.nbz, E.thr,
-                                                               q == tgt || last != 0u);
+    force_brick<float, BX, BY, BZ, NT, HCAP, MODE_FUSED, true, true>(
+        E.D, q, (int)w.item, E.nbx, E.nby, E.nbz, E.thr, q == tgt || last != 0u);
 }
 
 __global__ __launch_bounds__(256) void k_begin_batch(const BatchEnt *__restrict__ tab,
@@ -1086,8 +1168,14 @@ static hipError_t launch_force_g(const DevSys<T> &D, uint32_t q, int mode, hipSt
                            dim3(NT), 0, st, D, q, nbx, nby, nb, thr);
         break;
     case MODE_FUSED:
-        hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FUSED, IGEO>), dim3(nb),
-                           dim3(NT), 0, st, D, q, nbx, nby, nb, thr);
+        // The step kernel of mixed-precision cubic systems comes without bond
+        // code for systems that have no bonds.
+        if (IGEO && !D.bond_off)
+            hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FUSED, IGEO, !IGEO>),
+                               dim3(nb), dim3(NT), 0, st, D, q, nbx, nby, nb, thr);
+        else
+            hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_FUSED, IGEO>), dim3(nb),
+                               dim3(NT), 0, st, D, q, nbx, nby, nb, thr);
         break;
     default:
         hipLaunchKernelGGL((k_force<T, BX, BY, BZ, NT, HCAP, MODE_OBS, IGEO>), dim3(nb), dim3(NT),
