@@ -135,10 +135,23 @@ __device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 __device__ __forceinline__ double t_exp(double x) { return exp(x); }
 __device__ __forceinline__ float t_abs(float x) { return fabsf(x); }
-// Reciprocal square root: the hardware v_rsq_f32 (relative error below 1e-7,
-// measured) for FP32; correctly rounded 1/sqrt for FP64.
+// 1 / sqrt(a) for a > 0 in FP64: the hardware estimate refined by two Newton
+// steps, y <- y + y (1 - a y^2) / 2 (each doubles the correct bits; the
+// result is within an ulp or two, without a square root and a divide).
+__device__ __forceinline__ double rsqrt_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-a * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// Reciprocal square root of a positive argument: the hardware v_rsq_f32
+// (relative error below 1e-7, measured) for FP32; rsqrt_nr for FP64.
 __device__ __forceinline__ float t_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double t_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double t_rsqrt(double x) { return rsqrt_nr(x); }
 __device__ __forceinline__ float t_fma(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double t_fma(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ double t_abs(double x) { return fabs(x); }
@@ -257,18 +270,6 @@ __device__ __forceinline__ int64_t cell_linear(int cx, int cy, int cz, const int
 
 __device__ __forceinline__ double min_image(double d, double L) {
     return d - L * rint(d / L);
-}
-
-// 1 / sqrt(a) for a > 0: the hardware estimate refined by two Newton steps,
-// y <- y + y (1 - a y^2) / 2 (each doubles the correct bits).
-__device__ __forceinline__ double rsqrt_nr(double a) {
-    double y = __builtin_amdgcn_rsq(a);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-a * y, y, 1.0);
-        y = fma(0.5 * y, e, y);
-    }
-    return y;
 }
 
 // ---------------------------------------------------------------------------
