@@ -246,7 +246,10 @@ template <typename T, typename AT, int HCAP> struct Tile {
 // record of the chunk is loaded at once (one memory round trip, however full
 // the densest cell), its tag is parked in the tile's vx array, each record is
 // ranked among its cell's tags (distinct) from there, and after a barrier it
-// is stored at its rank.  All threads of the block must call it.
+// is stored at its rank.  Before that, one pass over the cells writes each
+// record's cell (into vy) and each cell's global index (into vz), so a record
+// finds its source slot with two LDS reads.  All threads of the block must
+// call it; the tile's arrays are free on entry.
 template <typename T, int HX, int HY, int NT, bool IGEO, typename AT, int HCAP>
 __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, int c0x, int c0y,
                                             int c0z, const int *s_hstart, int c0, int c1,
@@ -256,6 +259,14 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, in
     const int off0 = s_hstart[c0];
     const int m = s_hstart[c1] - off0;           // <= HCAP (chunk planning)
     uint32_t *park = reinterpret_cast<uint32_t *>(tl.vx);
+    uint16_t *rcell = reinterpret_cast<uint16_t *>(tl.vy);     // record -> halo cell
+    int32_t *gcell = reinterpret_cast<int32_t *>(tl.vz);      // halo cell - c0 -> global cell
+    for (int hc = c0 + (int)threadIdx.x; hc < c1; hc += NT) {
+        const int lo = s_hstart[hc] - off0, hi = s_hstart[hc + 1] - off0;
+        for (int k = lo; k < hi; ++k) rcell[k] = (uint16_t)hc;
+        gcell[hc - c0] = (int32_t)halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc);
+    }
+    __syncthreads();
     PRec<T> r[RPT];
     int hcell[RPT];
 #pragma unroll
@@ -263,12 +274,9 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, in
         const int t = (int)threadIdx.x + u * NT;
         hcell[u] = -1;
         if (t < m) {
-            // The cell holding chunk record t: the last cell whose start is
-            // <= t (empty cells share their successor's start).
-            const int hc = c0 + find_bin(s_hstart + c0, c1 - c0, t + off0);
+            const int hc = rcell[t];
             hcell[u] = hc;
-            r[u] = D.P[lay][halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc) * cap +
-                            (t + off0 - s_hstart[hc])];
+            r[u] = D.P[lay][(int64_t)gcell[hc - c0] * cap + (t + off0 - s_hstart[hc])];
         }
     }
 #pragma unroll
@@ -330,6 +338,9 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     // coordinate, (halo extent) * 2^29, must fit in 32 bits.
     constexpr int HMAX = HX > HY ? (HX > HZ ? HX : HZ) : (HY > HZ ? HY : HZ);
     static_assert(!IGEO || HMAX <= 7, "brick too large for the u32 brick frame");
+    // stage_cells keeps a u16 cell per record in vy and an i32 per halo cell
+    // in vz before the tile is filled.
+    static_assert(NHC <= HCAP && NHC < 65536, "halo too large for the staging maps");
     using AT = typename std::conditional<IGEO, LAI, LA<T>>::type;
 
     __shared__ int s_hstart[NHC + 1];
