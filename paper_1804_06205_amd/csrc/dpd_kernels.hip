@@ -247,24 +247,22 @@ template <typename T, typename AT, int HCAP> struct Tile {
 // the densest cell), its tag is parked in the tile's vx array, each record is
 // ranked among its cell's tags (distinct) from there, and after a barrier it
 // is stored at its rank.  Before that, one pass over the cells writes each
-// record's cell (into vy) and each cell's global index (into vz), so a record
-// finds its source slot with two LDS reads.  All threads of the block must
-// call it; the tile's arrays are free on entry.
+// record's cell into the tile's vy array, so a record finds its source slot
+// from that and the cell's global index (s_gcell) with two LDS reads.  All
+// threads of the block must call it; the tile's arrays are free on entry.
 template <typename T, int HX, int HY, int NT, bool IGEO, typename AT, int HCAP>
-__device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, int c0x, int c0y,
-                                            int c0z, const int *s_hstart, int c0, int c1,
-                                            const Tile<T, AT, HCAP> &tl) {
+__device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay,
+                                            const int *s_hstart, const int32_t *s_gcell, int c0,
+                                            int c1, const Tile<T, AT, HCAP> &tl) {
     constexpr int RPT = (HCAP + NT - 1) / NT;   // records per thread, at most
     const int cap = D.cap;
     const int off0 = s_hstart[c0];
     const int m = s_hstart[c1] - off0;           // <= HCAP (chunk planning)
     uint32_t *park = reinterpret_cast<uint32_t *>(tl.vx);
     uint16_t *rcell = reinterpret_cast<uint16_t *>(tl.vy);     // record -> halo cell
-    int32_t *gcell = reinterpret_cast<int32_t *>(tl.vz);      // halo cell - c0 -> global cell
     for (int hc = c0 + (int)threadIdx.x; hc < c1; hc += NT) {
         const int lo = s_hstart[hc] - off0, hi = s_hstart[hc + 1] - off0;
         for (int k = lo; k < hi; ++k) rcell[k] = (uint16_t)hc;
-        gcell[hc - c0] = (int32_t)halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc);
     }
     __syncthreads();
     PRec<T> r[RPT];
@@ -276,7 +274,7 @@ __device__ __forceinline__ void stage_cells(const DevSys<T> &D, uint32_t lay, in
         if (t < m) {
             const int hc = rcell[t];
             hcell[u] = hc;
-            r[u] = D.P[lay][(int64_t)gcell[hc - c0] * cap + (t + off0 - s_hstart[hc])];
+            r[u] = D.P[lay][(int64_t)s_gcell[hc] * cap + (t + off0 - s_hstart[hc])];
         }
     }
 #pragma unroll
@@ -338,12 +336,13 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     // coordinate, (halo extent) * 2^29, must fit in 32 bits.
     constexpr int HMAX = HX > HY ? (HX > HZ ? HX : HZ) : (HY > HZ ? HY : HZ);
     static_assert(!IGEO || HMAX <= 7, "brick too large for the u32 brick frame");
-    // stage_cells keeps a u16 cell per record in vy and an i32 per halo cell
-    // in vz before the tile is filled.
-    static_assert(NHC <= HCAP && NHC < 65536, "halo too large for the staging maps");
+    // stage_cells keeps a u16 halo cell per record in vy before the tile is
+    // filled.
+    static_assert(NHC < 65536, "halo too large for the staging map");
     using AT = typename std::conditional<IGEO, LAI, LA<T>>::type;
 
     __shared__ int s_hstart[NHC + 1];
+    __shared__ int32_t s_gcell[NHC];  // global cell of each halo cell (< 2^31 cells)
     __shared__ int s_ostart[NOC + 1];
     __shared__ int s_chunk[MAXCHUNK + 1];
     __shared__ int s_wave[2 * (NT / 64)];
@@ -379,14 +378,17 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     for (int hc = tid; hc < NHC; hc += NT) {
         const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
         int c = 0;
+        int32_t g = 0;
         if (hx <= ex + 1 && hy <= ey + 1 && hz <= ez + 1) {
-            c = (int)cnt[halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc)];
+            g = (int32_t)halo_cell<HX, HY>(hc, c0x, c0y, c0z, D.nc);
+            c = (int)cnt[g];
             if (c > cap) {
                 atomicOr(D.err, ERR_INDEX);
                 c = cap;
             }
         }
         s_hstart[hc] = c;
+        s_gcell[hc] = g;
         // Own cells (halo cells 1..B along each axis; those past a short
         // brick's extent hold no own particle).
         if (hx >= 1 && hx <= BX && hy >= 1 && hy <= BY && hz >= 1 && hz <= BZ)
@@ -458,23 +460,24 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     // (dz, dy) order, each three halo cells along x) as LDS ranges of the
     // chunk [clo, chi): first | end << 16, then a zero entry.
     // Built once per brick, or per chunk when the neighbourhood is split.
+    // One thread per own cell writes its ten entries (few threads, one pass).
     auto build_rows = [&](int clo, int chi, int off0) {
         if constexpr (IGEO) {
-            for (int e = tid; e < NOC * 10; e += NT) {
-                const int oc = e / 10, r = e - oc * 10;
-                uint32_t ent = 0u;
-                if (r < 9) {
-                    const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
-                    const int hr = ((oz + r / 3) * HY + (oy + r % 3)) * HX + ox;
+            for (int oc = tid; oc < NOC; oc += NT) {
+                const int ox = oc % BX, oy = (oc / BX) % BY, oz = oc / (BX * BY);
+                const int h0 = (oz * HY + oy) * HX + ox;
+#pragma unroll
+                for (int r = 0; r < 9; ++r) {
+                    const int hr = h0 + (r / 3) * (HY * HX) + (r % 3) * HX;
                     const int r0 = max(hr, clo), r1 = min(hr + 3, chi);
                     int jb = 0, je = 0;
                     if (r0 < r1) {
                         jb = s_hstart[r0] - off0;
                         je = s_hstart[r1] - off0;
                     }
-                    ent = (uint32_t)jb | ((uint32_t)je << 16);
+                    s_rows[oc * 10 + r] = (uint32_t)jb | ((uint32_t)je << 16);
                 }
-                s_rows[e] = ent;
+                s_rows[oc * 10 + 9] = 0u;
             }
         }
     };
@@ -496,15 +499,14 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             oxc = oc % BX;
             oyc = (oc / BX) % BY;
             ozc = oc / (BX * BY);
-            slot = cell_linear(c0x + oxc, c0y + oyc, c0z + ozc, D.nc) * cap +
+            slot = (int64_t)s_gcell[((ozc + 1) * HY + (oyc + 1)) * HX + (oxc + 1)] * cap +
                    (qi - s_ostart[oc]);
             pi = D.P[lay][slot];
         }
         if (base == 0 && nchunk == 1) {
             // Stage the whole neighbourhood once; the own-particle load above
             // is already in flight.
-            stage_cells<T, HX, HY, NT, IGEO, AT, HCAP>(D, lay, c0x, c0y, c0z, s_hstart, 0, NHC,
-                                                      tile);
+            stage_cells<T, HX, HY, NT, IGEO, AT, HCAP>(D, lay, s_hstart, s_gcell, 0, NHC, tile);
             __syncthreads();
         }
         // Brick-frame coordinates of i (IGEO).
@@ -625,8 +627,8 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
             const int off0 = s_hstart[clo];
             if (nchunk > 1) {
                 __syncthreads();
-                stage_cells<T, HX, HY, NT, IGEO, AT, HCAP>(D, lay, c0x, c0y, c0z, s_hstart, clo,
-                                                          chi, tile);
+                stage_cells<T, HX, HY, NT, IGEO, AT, HCAP>(D, lay, s_hstart, s_gcell, clo, chi,
+                                                          tile);
                 if constexpr (IGEO) build_rows(clo, chi, off0);
                 __syncthreads();
             }
