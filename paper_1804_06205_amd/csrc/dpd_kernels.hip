@@ -60,10 +60,65 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // Exclusive prefix sums of a[0..ma) and b[0..mb) in place, in one pass
-// (ma <= NT * IPTA, mb <= NT * IPTB); a[ma] and b[mb] get the totals.
-// s_wave holds 2 * NT / 64 ints.  All threads of the block must call it.
+// (ma <= NT * IPTA, mb <= NT * IPTB); a[ma] and b[mb] get the totals.  Both
+// totals must stay below 2^16: the two scans run as one, on a + b * 2^16.
+// s_wave holds NT / 64 ints.  All threads of the block must call it.
 template <int NT, int IPTA, int IPTB>
 __device__ void block_scan2(int *a, int ma, int *b, int mb, int *s_wave) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    int va[IPTA], vb[IPTB];
+    uint32_t sab = 0u;
+#pragma unroll
+    for (int k = 0; k < IPTA; ++k) {
+        const int idx = tid * IPTA + k;
+        va[k] = idx < ma ? a[idx] : 0;
+        sab += (uint32_t)va[k];
+    }
+#pragma unroll
+    for (int k = 0; k < IPTB; ++k) {
+        const int idx = tid * IPTB + k;
+        vb[k] = idx < mb ? b[idx] : 0;
+        sab += (uint32_t)vb[k] << 16;
+    }
+    uint32_t iab = sab;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(iab, off, 64);
+        if (lane >= off) iab += t;
+    }
+    if (lane == 63) s_wave[wid] = (int)iab;
+    __syncthreads();
+    uint32_t wab = 0u;
+    for (int w = 0; w < wid; ++w) wab += (uint32_t)s_wave[w];
+    const uint32_t rab = wab + iab - sab;
+    int ra = (int)(rab & 0xFFFFu), rb = (int)(rab >> 16);
+#pragma unroll
+    for (int k = 0; k < IPTA; ++k) {
+        const int idx = tid * IPTA + k;
+        if (idx < ma) a[idx] = ra;
+        ra += va[k];
+    }
+#pragma unroll
+    for (int k = 0; k < IPTB; ++k) {
+        const int idx = tid * IPTB + k;
+        if (idx < mb) b[idx] = rb;
+        rb += vb[k];
+    }
+    if (tid == NT - 1) {
+        a[ma] = ra;
+        b[mb] = rb;
+    }
+    __syncthreads();
+}
+
+// Exclusive prefix sums of a[0..ma) and b[0..mb) in place, in one pass
+// (ma <= NT * IPTA, mb <= NT * IPTB); a[ma] and b[mb] get the totals.
+// s_wave holds 2 * NT / 64 ints.  All threads of the block must call it.
+// Used when a total may reach 2^16 (block_scan2 above packs both into one).
+template <int NT, int IPTA, int IPTB>
+__device__ void block_scan2_wide(int *a, int ma, int *b, int mb, int *s_wave) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
@@ -407,7 +462,11 @@ __device__ __forceinline__ void force_brick(const DevSys<T> &D, uint32_t q, int 
     }
     __syncthreads();
     if (s_flag) return;
-    block_scan2<NT, IPT_H, IPT_O>(s_hstart, NHC, s_ostart, NOC, s_wave);
+    // Halo counts are clamped to cap, so NHC * cap bounds both totals.
+    if ((int64_t)NHC * cap < 65536)
+        block_scan2<NT, IPT_H, IPT_O>(s_hstart, NHC, s_ostart, NOC, s_wave);
+    else
+        block_scan2_wide<NT, IPT_H, IPT_O>(s_hstart, NHC, s_ostart, NOC, s_wave);
     const int nown = s_ostart[NOC];
     // Chunks of whole halo cells that fit the LDS tile, in cell order: one
     // chunk unless the neighbourhood is unusually dense (then planned by one
@@ -955,20 +1014,34 @@ void k_force(DevSys<T> D, uint32_t q, int nbx, int nby, int nbricks, uint64_t th
 }
 
 // begin: integrate-1 and binning of every particle of resting state q; one
-// thread per cell g of layout q.
+// thread per cell g of layout q (a wave's appends then go to many different
+// cells).  The cell's records are read four at a time, their loads issued
+// together, rather than one round trip per record.
 template <typename T>
 __device__ __forceinline__ void begin_cell(const DevSys<T> &D, uint32_t q, int64_t g) {
     if (g >= D.ncells) return;
     const uint32_t lay = q & 1u;
     D.count[count_index(q, 2u)][g] = 0u;
     const uint32_t n = min(D.count[count_index(q, 0u)][g], (uint32_t)D.cap);
-    for (uint32_t k = 0; k < n; ++k) {
-        const int64_t slot = g * D.cap + k;
-        const SRec<T> s = D.S[lay][slot];
-        const PRec<T> p = D.P[lay][slot];
-        const bool bonded = D.bond_off && D.bond_off[p.tag + 1] > D.bond_off[p.tag];
-        drift_and_bin<T>(D, q, s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz, p.tag, p.type,
-                         bonded);
+    for (uint32_t k0 = 0; k0 < n; k0 += 4u) {
+        SRec<T> s[4];
+        PRec<T> p[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4u; ++u) {
+            if (k0 + u < n) {
+                const int64_t slot = g * D.cap + k0 + u;
+                s[u] = D.S[lay][slot];
+                p[u] = D.P[lay][slot];
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4u; ++u) {
+            if (k0 + u >= n) break;
+            const bool bonded =
+                D.bond_off && D.bond_off[p[u].tag + 1] > D.bond_off[p[u].tag];
+            drift_and_bin<T>(D, q, s[u].x, s[u].y, s[u].z, s[u].vx, s[u].vy, s[u].vz, s[u].fx,
+                             s[u].fy, s[u].fz, p[u].tag, p[u].type, bonded);
+        }
     }
 }
 

@@ -602,6 +602,26 @@ def test_chunked_neighbourhoods_give_bitwise_identical_steps(rho):
                 np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_large_cell_capacity_gives_bitwise_identical_steps(precision):
+    # With 1024 slots per cell a brick's halo counts may add up to 2^16 or
+    # more, so the brick prologue takes its wide prefix scan instead of the
+    # packed one; the layout is padded differently, which the tag-order
+    # staging hides: every combination gives the same bits.
+    w = W.peptide(10.0, seed=51, nchains=5, nbeads=20)
+    got = {}
+    for cap in (0, 1024):
+        for v in (1, 4):
+            with dpd.System.from_workload(w, precision=precision, cell_capacity=cap) as g:
+                g.set_variant(v)
+                g.step(6)
+                got[cap, v] = g.get_state()
+    ref = got[0, 1]
+    for key, st in got.items():
+        for a, b in zip(st[:3], ref[:3]):
+            np.testing.assert_array_equal(a, b, err_msg=str(key))
+
+
 def test_autotune_leaves_the_state_unchanged():
     w = W.melt(12.0, seed=52)
     with dpd.System.from_workload(w) as g:
