@@ -159,11 +159,22 @@ def test_pair_count_exact_on_quantized_positions(precision):
 # Single force evaluations.
 # --------------------------------------------------------------------------
 
+def _binary_fluid(L, seed):
+    # Two particle types and no bonds: the step kernel built without the bond
+    # code, with the a_ij table (a_AA = a_BB = 25, a_AB = 40).
+    w = W.fluid(L, seed=seed, name=f"binary_L{L:g}")
+    w.types = (np.arange(w.n) % 2).astype(np.uint8)
+    w.ntypes = 2
+    w.a = np.array([[25.0, 40.0], [40.0, 25.0]])
+    return w
+
+
 def _cases():
     return {
         "fluid_L10": W.fluid(10.0, seed=1),
         "fluid_L3": W.fluid(3.0, seed=2),
         "fluid_L7.5": W.fluid(7.5, seed=3),
+        "binary_L8": _binary_fluid(8.0, 9),
         "melt_L8": W.melt(8.0, seed=4),
         "peptide_L8": W.peptide(8.0, seed=5, nchains=6, nbeads=20),
         "helix_L6": W.helix(6.0, seed=6, beads=12),
@@ -232,7 +243,7 @@ def test_momentum_conservation():
 # Trajectories.
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["fluid_L10", "melt_L8", "peptide_L8", "helix_L6",
+@pytest.mark.parametrize("name", ["fluid_L10", "binary_L8", "melt_L8", "peptide_L8", "helix_L6",
                                   "fluid_6x7.5x8", "peptide_6x7.5x8"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_ten_step_trajectory(name, precision):
@@ -567,7 +578,7 @@ def test_dense_box_uses_chunked_neighbourhoods():
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-@pytest.mark.parametrize("system", ["peptide", "melt", "sweep_chains"])
+@pytest.mark.parametrize("system", ["peptide", "melt", "sweep_chains", "binary"])
 def test_every_brick_variant_gives_bitwise_identical_steps(precision, system):
     # The bond terms are scheduled per wave: dealt one per lane where a few
     # lanes own several records (peptide chains in solvent), each lane's own
@@ -577,7 +588,8 @@ def test_every_brick_variant_gives_bitwise_identical_steps(precision, system):
     # either schedule, and the sums must agree to the bit.
     w = {"peptide": lambda: W.peptide(10.0, seed=51, nchains=5, nbeads=20),
          "melt": lambda: W.melt(8.0, seed=52),
-         "sweep_chains": lambda: W.sweep_box(5000, chains=True)}[system]()
+         "sweep_chains": lambda: W.sweep_box(5000, chains=True),
+         "binary": lambda: _binary_fluid(10.0, 54)}[system]()
     ref = None
     for v in range(len(dpd.variants())):
         with dpd.System.from_workload(w, precision=precision) as g:
